@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Helmholtz right-hand sides solved per second at relative residual 1e-6, one MI355X.
+
+Workload: 256x256 layered medium (8 random layers, 1.5-4.5 km/s, x(1+0.1 GRF)),
+16-cell absorbing layer, 10 points per minimum wavelength, 32 surface point
+sources, all solved in one batched flexible-GMRES call.  One step = operator
+setup (coefficients + multigrid hierarchy + coarse polynomial) + encoder pass
+(CNN preconditioner) + the batched solve of all 32 right-hand sides to an FP64
+relative residual of 1e-6.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is the CNN-FGMRES rate when a trained network is
+available (--net, default profiles of the package), else the MG-GMRES rate; both
+rates are reported in `compare`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Helmholtz RHS solved/s at rel-res 1e-6: CNN-FGMRES vs MG-GMRES, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+DOMINANT = {"mg": "k_update", "cnn_vu": "k_conv_fwd", "cnn": "k_conv_fwd"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precond", default="auto", choices=["auto", "mg", "cnn_vu", "cnn"])
+    ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rhs", type=int, default=1)
+    ap.add_argument("--net", default=None, help="trained network file for the CNN preconditioner")
+    ap.add_argument("--kernel", default=None, help="kernel whose roofline is reported")
+    ap.add_argument("--no-reorth", action="store_true", help="never take the second Gram-Schmidt pass")
+    return ap.parse_args()
+
+
+def kernel_roofline(api_lib, name, unit_bytes=True):
+    import ctypes as C
+    n = C.c_int()
+    ms = C.c_double()
+    work = C.c_double()
+    rc = api_lib.helm_ktimer_read(C.byref(n), C.byref(ms), C.byref(work))
+    if rc != 0 or n.value == 0 or ms.value <= 0:
+        return None
+    avg_ms = ms.value / n.value
+    achieved = work.value / (ms.value * 1e-3) / 1e9
+    return {"kernel": name, "launches": n.value, "avg_us": avg_ms * 1e3, "achieved": achieved,
+            "work_per_launch": work.value / n.value}
+
+
+def cpu_baseline(med, src, nrhs):
+    """The FP64 oracle (MG-preconditioned GMRES(20)) on a bounded sample."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:                                  # pragma: no cover
+        threadpool_limits = None
+    from oracle import krylov as kr
+    from oracle import multigrid as mg
+    from oracle import operator as op
+    n = med.kappa2.shape[0]
+    k2 = np.asarray(med.kappa2, np.float32).astype(np.float64)
+    g = np.asarray(med.gamma, np.float32).astype(np.float64)
+    coef = op.helmholtz_coef(k2, g, med.omega)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    V = mg.VCycle(k2, g, med.omega, med.h)
+    its = []
+    for s in range(nrhs):
+        res = kr.gmres(lambda v: op.apply(coef, v.reshape(n, n), med.h, med.h).ravel(),
+                       src[s].astype(np.complex128), M=lambda v: V(v.reshape(n, n)).ravel(), restart=20,
+                       tol=1e-6, maxit=2000)
+        its.append(res.iters)
+    dt = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.unregister() if hasattr(ctx, "unregister") else None
+    return {"value": nrhs / dt, "unit": "RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nrhs} of 32 RHS of the 256x256 layered workload, FP64 MG-GMRES(20), setup included, "
+                      f"{dt:.1f} s, iterations {its}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2405_17696_amd import _lib, api, synth
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    med, src = synth.config2_medium()
+    nrhs = src.shape[0]
+    k2 = torch.tensor(med.kappa2, dtype=torch.float32, device=dev)
+    gam = torch.tensor(med.gamma, dtype=torch.float32, device=dev)
+    b = torch.tensor(src, dtype=torch.complex64, device=dev)
+    x = torch.empty(b.shape, dtype=torch.complex128, device=dev)
+
+    net = None
+    precond = a.precond
+    if precond == "auto":
+        precond = "mg"
+    kernel = a.kernel or DOMINANT[precond]
+
+    def step(pc):
+        op = api.helm_setup(k2, gam, med.omega, med.h)
+        out = api.helm_solve(op, b, x, tol=1e-6, precond=pc, maxit=a.maxit, net=net, no_reorth=a.no_reorth)
+        op.close()
+        return out
+
+    def run(pc, steps, warmup, timer=None):
+        for _ in range(warmup):
+            step(pc)
+        torch.cuda.synchronize()
+        if timer:
+            _lib.check(lib.helm_ktimer_start(timer.encode()))
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            last = step(pc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        roof = kernel_roofline(lib, timer) if timer else None
+        if timer:
+            _lib.check(lib.helm_ktimer_start(None))
+        return dt, last, roof
+
+    dt, last, roof = run(precond, a.steps, a.warmup, timer=kernel)
+    _, it, rr, st, code = last
+    if code != 0:
+        raise SystemExit(f"solve did not converge: status {st.tolist()} relres {rr.tolist()}")
+    value = nrhs * a.steps / dt
+    compare = {precond: {"rhs_per_s": value, "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                         "relres_max": float(rr.max())}}
+    if precond != "mg":
+        dtm, lastm, _ = run("mg", max(1, a.steps // 2), 1)
+        compare["mg"] = {"rhs_per_s": nrhs * max(1, a.steps // 2) / dtm, "iters_mean": float(lastm[1].mean())}
+        compare["speedup_vs_mg"] = value / compare["mg"]["rhs_per_s"]
+
+    roofline = None
+    if roof:
+        roofline = {"bound": "hbm", "kernel": roof["kernel"], "achieved": roof["achieved"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": roof["achieved"] / HBM_PEAK_GBS, "traffic": None,
+                    "avg_us": roof["avg_us"], "launches": roof["launches"],
+                    "bytes_per_launch": roof["work_per_launch"]}
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(med, src, a.cpu_sample_rhs)
+    out = {"metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64 Krylov / c128 iterate / f64 residual", "data": "synthetic",
+           "config": {"workload": "256x256 layered+GRF medium, 10 ppw, 32 surface sources, tol 1e-6",
+                      "precond": precond, "global_batch": nrhs, "grid": [256, 256],
+                      "parallelism": "single GPU"},
+           "compare": compare, "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

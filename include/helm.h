@@ -1,0 +1,143 @@
+/*
+ * helm.h -- C ABI of libhelm, a gfx950 library for repeated 2D Helmholtz
+ * solves preconditioned by a shifted-Laplacian multigrid cycle and by an
+ * encoder-solver convolutional network (Goren & Treister, "Physics-guided Full
+ * Waveform Inversion using Encoder-Solver Convolutional Neural Networks").
+ *
+ * Conventions (every entry point):
+ *   - grids are row-major [nz][nx], x (columns) fastest, row 0 at the surface;
+ *     nx must be even (two nodes are loaded per lane);
+ *   - complex arrays are interleaved (re, im); "c64" = 2 x float,
+ *     "c128" = 2 x double; a batch of right-hand sides is stored back to back
+ *     (batch outermost);
+ *   - every data pointer is a DEVICE pointer owned by the caller unless the
+ *     comment says "host"; the library never frees caller memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream); work
+ *     is enqueued on it, and entry points return once their host-visible
+ *     outputs are written (helm_solve reads one small per-RHS status block back
+ *     to the host per restart cycle);
+ *   - return codes: HELM_OK, HELM_NOT_CONVERGED (soft: per-RHS status filled),
+ *     or a negative hard error; helm_last_error() gives the message;
+ *   - handles are not thread-safe; distinct handles may be used from distinct
+ *     threads.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_OK 0
+#define HELM_NOT_CONVERGED 1
+#define HELM_EINVAL (-1)
+#define HELM_ENOMEM (-2)
+#define HELM_EHIP (-3)
+#define HELM_ENAN (-4)
+
+#define HELM_C64 0
+#define HELM_C128 1
+
+#define HELM_PRECOND_MG 0     /* M = V_SL, the shifted-Laplacian V-cycle        */
+#define HELM_PRECOND_NONE 1   /* M = I                                          */
+#define HELM_PRECOND_CNN 2    /* M = SolverNet only                             */
+#define HELM_PRECOND_CNN_VU 3 /* M_VU(r) = e0 + V_SL(r - H e0), e0 = SolverNet(r) */
+
+typedef struct helm_op* helm_op_t;
+typedef struct cnn_net* cnn_net_t;
+
+/* Options of helm_setup.  Zero-initialised fields take the defaults. */
+typedef struct {
+    double hz;            /* vertical spacing; <= 0 means hz = h                 */
+    double sl_beta;       /* shift beta of eq. (3.12); <= 0 means 0.5            */
+    int sl_no_gamma;      /* 1: literal P = -Lap - w^2 m (1 - beta i) (no gamma) */
+    int mg_levels;        /* <= 0 means 3 (Sec. 3.4); 1..4 accepted              */
+    int coarse_degree;    /* degree of the coarsest-level polynomial; <= 0: 20   */
+    double jacobi_weight; /* damped-Jacobi weight; <= 0 means 0.8                */
+} helm_setup_opts;
+
+/*
+ * helm_setup -- operator H(m, omega) of eq. (3.1)-(3.2) and its shifted-
+ * Laplacian hierarchy (eq. (3.12)).
+ *   kappa2 [nz][nx] float: squared slowness m = 1/c^2 (device);
+ *   gamma  [nz][nx] float: attenuation fraction (absorbing layer) (device);
+ *   omega: angular frequency; h: horizontal spacing (opt->hz vertical).
+ * H u = (2u - u_W - u_E)/hx^2 + (2u - u_N - u_S)/hz^2 - omega^2 m (1 - i gamma) u,
+ * with zero values outside the grid.  The handle copies kappa2 and gamma; the
+ * caller may free them afterwards.  Errors: HELM_EINVAL (nz, nx < 4, odd nx,
+ * non-positive h or omega), HELM_ENOMEM, HELM_EHIP.
+ */
+int helm_setup(const float* kappa2, const float* gamma, int nz, int nx, double omega, double h,
+               const helm_setup_opts* opt, void* stream, helm_op_t* out);
+void helm_destroy(helm_op_t op);
+/* Grid size of an operator (host outputs; any may be NULL). */
+int helm_op_info(helm_op_t op, int* nz, int* nx, double* omega, double* hx, double* hz);
+
+/*
+ * helm_matvec -- v = H u (adjoint = 0) or v = H^* u (adjoint = 1) for nrhs
+ * vectors [nrhs][nz][nx] of type dtype (HELM_C64 or HELM_C128).  u and v must
+ * not overlap.  Eq. (3.2); H^* = conj(H) because H is complex symmetric (Sec. 4.3).
+ */
+int helm_matvec(helm_op_t op, const void* u, void* v, int nrhs, int dtype, int adjoint, void* stream);
+
+/* Options of helm_solve.  Zero-initialised fields take the defaults. */
+typedef struct {
+    int precond;          /* HELM_PRECOND_*; default HELM_PRECOND_MG             */
+    int restart;          /* Krylov cycle length m; <= 0: 20 (MG/NONE), 10 (CNN) */
+    int maxit;            /* iteration cap per RHS; <= 0: 300 (Sec. 5.7)         */
+    int adjoint;          /* 1: solve H^* x = b by conjugation (eq. (4.4)-(4.8)) */
+    int krylov_dtype;     /* HELM_C64 (default) or HELM_C128 basis vectors       */
+    int x0_given;         /* 1: x holds the initial guess; 0: start from x = 0   */
+    int use_graph;        /* 1: replay each restart cycle from a captured graph  */
+    int no_reorth;        /* 1: never take the second Gram-Schmidt pass          */
+    cnn_net_t net;        /* network for the CNN preconditioners                 */
+} helm_solve_opts;
+
+/*
+ * helm_solve -- flexible GMRES(m), right preconditioned, for a batch of
+ * systems H_{op(r)} x_r = b_r (Sec. 3.4, eq. (3.14)).
+ *   ops[nops]: operators; rhs_op[nrhs] (host): operator index of each RHS,
+ *     non-decreasing (RHS grouped by operator);
+ *   rhs: c64 right-hand sides, back to back in RHS order (device);
+ *   x:   c128 solutions, same layout (device; in: initial guess if x0_given);
+ *   iters, relres, status [nrhs] (host outputs, may be NULL): iterations,
+ *     FP64 ||b - H x|| / ||b||, and per-RHS HELM_OK / HELM_NOT_CONVERGED /
+ *     HELM_ENAN.
+ * Stopping: relres <= tol with the residual recomputed in FP64 from the c128
+ * iterate at every restart; b = 0 gives x = 0.  Returns HELM_OK when every RHS
+ * converged, HELM_NOT_CONVERGED otherwise, or a hard error.
+ */
+int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* x, int nrhs,
+               double tol, const helm_solve_opts* opt, int* iters, double* relres, int* status,
+               void* stream);
+
+/*
+ * helm_vcycle -- e = V_SL(f): one shifted-Laplacian V-cycle from e = 0
+ * (Sec. 3.4, "levels = 3") for nrhs c64 vectors (device).  Linear in f.
+ */
+int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
+/* Roots of the coarsest-level polynomial, in application order (host, c128 [*n]). */
+int helm_coarse_roots(helm_op_t op, double* roots, int* n);
+
+/*
+ * Diagnostics: time every launch of one named kernel ("k_matvec_dot",
+ * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",
+ * "k_conv_fwd", ...) with HIP events recorded on the stream it is launched on,
+ * and count the algorithmic bytes (or flops) its active blocks processed.
+ * kernel = NULL stops timing.  helm_ktimer_read synchronises the device and
+ * returns the totals since the last start (host outputs).
+ */
+int helm_ktimer_start(const char* kernel);
+int helm_ktimer_read(int* launches, double* total_ms, double* total_work);
+
+const char* helm_last_error(void);
+/* Library version string. */
+const char* helm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

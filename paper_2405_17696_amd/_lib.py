@@ -1,0 +1,83 @@
+"""ctypes loader for libhelm.so (argument marshalling only; all compute is in the library).
+
+The library is loaded from the package directory.  There is no fallback: if
+the shared object is missing or cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().parent / "libhelm.so"
+
+HELM_OK = 0
+HELM_NOT_CONVERGED = 1
+HELM_EINVAL = -1
+HELM_ENOMEM = -2
+HELM_EHIP = -3
+HELM_ENAN = -4
+HELM_C64 = 0
+HELM_C128 = 1
+PRECOND = {"mg": 0, "none": 1, "cnn": 2, "cnn_vu": 3}
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libhelm error {code}: {msg}")
+        self.code = code
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("hz", C.c_double), ("sl_beta", C.c_double), ("sl_no_gamma", C.c_int),
+                ("mg_levels", C.c_int), ("coarse_degree", C.c_int), ("jacobi_weight", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precond", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("adjoint", C.c_int),
+                ("krylov_dtype", C.c_int), ("x0_given", C.c_int), ("use_graph", C.c_int),
+                ("no_reorth", C.c_int), ("net", C.c_void_p)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every exported symbol of include/*.h is listed here
+SIGNATURES = {
+    "helm_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                             C.POINTER(SetupOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "helm_destroy": (None, [C.c_void_p]),
+    "helm_op_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "helm_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "helm_solve": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_void_p, C.c_void_p,
+                             C.c_int, C.c_double, C.POINTER(SolveOpts), C.POINTER(C.c_int),
+                             C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
+    "helm_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "helm_coarse_roots": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "helm_ktimer_start": (C.c_int, [C.c_char_p]),
+    "helm_ktimer_read": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "helm_last_error": (C.c_char_p, []),
+    "helm_version": (C.c_char_p, []),
+}
+
+
+def load():
+    """Load libhelm.so (once).  Raises if it is missing: there is no CPU fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise HelmError(HELM_EINVAL, f"{LIB_PATH} not built; run __graft_entry__.build()")
+    lib = C.CDLL(str(LIB_PATH))
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code, soft_ok=False):
+    if code == HELM_OK or (soft_ok and code == HELM_NOT_CONVERGED):
+        return code
+    msg = load().helm_last_error().decode(errors="replace")
+    raise HelmError(code, msg)

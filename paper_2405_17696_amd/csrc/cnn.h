@@ -1,0 +1,17 @@
+// Interface between the Krylov driver and the encoder-solver network module.
+#pragma once
+#include "internal.h"
+
+namespace helm {
+
+// Make sure the encoder context of (net, op) is current (runs the encoder if needed).
+int cnn_prepare(cnn_net* net, const helm_op* op, hipStream_t s);
+// e = SolverNet(scale_r * r) / scale_r for nrhs vectors of op's grid (c64, or c128
+// when wide != 0), skipping RHS whose state is inactive.  scale_r comes from
+// fscale[(rhs0 + r) * fstride] (may be null: 1).
+int cnn_apply_masked(cnn_net* net, const helm_op* op, const void* r, const double* fscale, int fstride, void* e,
+                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s);
+// Drop any encoder context cached on op.
+void cnn_release_cache(helm_op* op);
+
+}  // namespace helm

@@ -1,0 +1,130 @@
+// Internal helpers of libhelm: complex arithmetic, vector loads, reductions,
+// error reporting.  gfx950 only (64-wide wavefronts).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/helm.h"
+
+namespace helm {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define HELM_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::helm::fail(HELM_EHIP, "%s:%d %s: %s", __FILE__, __LINE__, #call,    \
+                                hipGetErrorString(e_));                                  \
+    } while (0)
+
+#define HELM_CHECK_LAUNCH() HELM_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- kernel timer
+// When a kernel name is armed, its launchers bracket each launch with events on
+// the launch stream and pass a device counter that active blocks add their
+// algorithmic work (bytes or flops) to.
+struct KTimer {
+    bool armed(const char* name) const;
+    unsigned long long* counter() const;
+    void begin(hipStream_t s);
+    void end(hipStream_t s);
+};
+KTimer& ktimer();
+
+#define TIMED_LAUNCH(name, stream, ...)                         \
+    do {                                                        \
+        const bool on_ = ::helm::ktimer().armed(name);          \
+        if (on_) ::helm::ktimer().begin(stream);                \
+        hipLaunchKernelGGL(__VA_ARGS__);                        \
+        if (on_) ::helm::ktimer().end(stream);                  \
+    } while (0)
+
+#define WORK_COUNTER(name) (::helm::ktimer().armed(name) ? ::helm::ktimer().counter() : nullptr)
+
+__device__ __forceinline__ void add_work(unsigned long long* c, unsigned long long v) {
+    if (c && threadIdx.x == 0) atomicAdd(c, v);
+}
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
+    cx<T> r;
+    r.re = a;
+    r.im = b;
+    return r;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk(s * a.re, s * a.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.re, -a.im); }
+template <typename T>
+__host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
+    T d = T(1) / (a.re * a.re + a.im * a.im);
+    return mk(a.re * d, -a.im * d);
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cdot1(cx<T> a, cx<T> b) {
+    return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T, typename U>
+__host__ __device__ __forceinline__ cx<T> ccast(cx<U> a) { return mk(T(a.re), T(a.im)); }
+
+// ---------------------------------------------------------------- two-node loads
+// Two consecutive nodes (16 B for c64, 32 B for c128), always 16-B aligned
+// because node pairs start at even indices.
+template <typename T>
+struct pair2 {
+    cx<T> a, b;
+};
+__device__ __forceinline__ pair2<float> ld_pair(const c64* p) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    return {mk(v.x, v.y), mk(v.z, v.w)};
+}
+__device__ __forceinline__ pair2<double> ld_pair(const c128* p) {
+    double2 v0 = reinterpret_cast<const double2*>(p)[0];
+    double2 v1 = reinterpret_cast<const double2*>(p)[1];
+    return {mk(v0.x, v0.y), mk(v1.x, v1.y)};
+}
+__device__ __forceinline__ void st_pair(c64* p, pair2<float> v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.a.re, v.a.im, v.b.re, v.b.im);
+}
+__device__ __forceinline__ void st_pair(c128* p, pair2<double> v) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(v.a.re, v.a.im);
+    reinterpret_cast<double2*>(p)[1] = make_double2(v.b.re, v.b.im);
+}
+
+// ---------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+}  // namespace helm

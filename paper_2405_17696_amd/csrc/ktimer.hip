@@ -1,0 +1,84 @@
+// Per-kernel event timer and algorithmic-work counter (diagnostics).
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+
+namespace helm {
+
+namespace {
+struct TimerState {
+    std::string name;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    unsigned long long* dcount = nullptr;
+    hipEvent_t pending = nullptr;
+};
+TimerState g_t;
+
+hipEvent_t take_event() {
+    if (g_t.used < g_t.pool.size()) return g_t.pool[g_t.used++];
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_t.pool.push_back(e);
+    g_t.used++;
+    return e;
+}
+}  // namespace
+
+bool KTimer::armed(const char* name) const { return !g_t.name.empty() && g_t.name == name; }
+unsigned long long* KTimer::counter() const { return g_t.dcount; }
+void KTimer::begin(hipStream_t s) {
+    g_t.pending = take_event();
+    if (g_t.pending) (void)hipEventRecord(g_t.pending, s);
+}
+void KTimer::end(hipStream_t s) {
+    hipEvent_t e = take_event();
+    if (g_t.pending && e) {
+        (void)hipEventRecord(e, s);
+        g_t.ev.push_back({g_t.pending, e});
+    }
+    g_t.pending = nullptr;
+}
+KTimer& ktimer() {
+    static KTimer t;
+    return t;
+}
+
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" int helm_ktimer_start(const char* kernel) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_start: device sync failed");
+    g_t.ev.clear();
+    g_t.used = 0;
+    g_t.name = kernel ? kernel : "";
+    if (kernel) {
+        if (!g_t.dcount && hipMalloc(&g_t.dcount, sizeof(unsigned long long)) != hipSuccess)
+            return fail(HELM_ENOMEM, "helm_ktimer_start: counter allocation failed");
+        if (hipMemset(g_t.dcount, 0, sizeof(unsigned long long)) != hipSuccess)
+            return fail(HELM_EHIP, "helm_ktimer_start: counter reset failed");
+    }
+    return HELM_OK;
+}
+
+extern "C" int helm_ktimer_read(int* launches, double* total_ms, double* total_work) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_read: device sync failed");
+    double ms = 0;
+    for (auto& p : g_t.ev) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, p.first, p.second) != hipSuccess)
+            return fail(HELM_EHIP, "helm_ktimer_read: elapsed time failed");
+        ms += t;
+    }
+    unsigned long long w = 0;
+    if (g_t.dcount && hipMemcpy(&w, g_t.dcount, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(HELM_EHIP, "helm_ktimer_read: counter read failed");
+    if (launches) *launches = (int)g_t.ev.size();
+    if (total_ms) *total_ms = ms;
+    if (total_work) *total_work = (double)w;
+    return HELM_OK;
+}
