@@ -92,7 +92,7 @@ typedef struct {
     int krylov_dtype;     /* HELM_C64 (default) or HELM_C128 basis vectors       */
     int x0_given;         /* 1: x holds the initial guess; 0: start from x = 0   */
     int use_graph;        /* 1: replay each restart cycle from a captured graph  */
-    int no_reorth;        /* 1: never take the second Gram-Schmidt pass          */
+    int reorth;           /* 1: second Gram-Schmidt pass when ||w|| drops by 0.7 */
     cnn_net_t net;        /* network for the CNN preconditioners                 */
 } helm_solve_opts;
 

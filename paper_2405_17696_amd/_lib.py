@@ -35,7 +35,7 @@ class SetupOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("adjoint", C.c_int),
                 ("krylov_dtype", C.c_int), ("x0_given", C.c_int), ("use_graph", C.c_int),
-                ("no_reorth", C.c_int), ("net", C.c_void_p)]
+                ("reorth", C.c_int), ("net", C.c_void_p)]
 
 
 _lib = None

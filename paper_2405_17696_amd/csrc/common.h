@@ -36,6 +36,11 @@ struct KTimer {
     unsigned long long* counter() const;
     void begin(hipStream_t s);
     void end(hipStream_t s);
+    // Add the elapsed time of event pairs recorded inside a replayed graph
+    // (call after the replay has completed).
+    void harvest();
+    // Forget the event pairs of a previous graph (called before a new capture).
+    void new_capture();
 };
 KTimer& ktimer();
 

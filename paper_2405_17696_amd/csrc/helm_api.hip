@@ -76,6 +76,23 @@ struct SolveWork {
 static SolveWork g_work;
 static std::mutex g_mutex;
 
+struct GraphHolder {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphHolder() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Streams cannot be captured when they are the legacy default stream; graph
+// replays then run on a library stream ordered after the caller's stream.
+static hipStream_t graph_stream() {
+    static hipStream_t gs = nullptr;
+    if (!gs) (void)hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+    return gs;
+}
+
 template <typename T>
 static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* xv, int nrhs,
                       double tol, const helm_solve_opts& o, int* iters, double* relres, int* status, hipStream_t s) {
@@ -171,7 +188,7 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     a.maxblk = maxblk;
     a.maxit = o.maxit;
     a.conjop = 0;
-    a.no_reorth = o.no_reorth;
+    a.reorth = o.reorth;
     a.Ntot = Ntot;
     a.tol = tol;
     a.V = (cx<T>*)W.V.p;
@@ -233,37 +250,59 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
         return HELM_OK;
     };
 
-    bool first = true;
+    // One restart cycle (Arnoldi steps, least squares, update of x) followed
+    // by the true residual that opens the next cycle.  Eager, or replayed
+    // from a graph captured on the first cycle.
+    auto cycle_body = [&]() -> int {
+        int r;
+        for (int j = 0; j < m; ++j) {
+            if ((r = precond(j))) return r;
+            for (size_t gi = 0; gi < groups.size(); ++gi)
+                if ((r = launch_matvec_dot<T>(ga[gi], groups[gi].n, a, j, s))) return r;
+            for (size_t gi = 0; gi < groups.size(); ++gi)
+                if ((r = launch_update<T>(ga[gi], groups[gi].n, a, j, 1, s))) return r;
+            if (o.reorth) {
+                for (size_t gi = 0; gi < groups.size(); ++gi)
+                    if ((r = launch_dot2<T>(ga[gi], groups[gi].n, a, j, s))) return r;
+                for (size_t gi = 0; gi < groups.size(); ++gi)
+                    if ((r = launch_update<T>(ga[gi], groups[gi].n, a, j, 2, s))) return r;
+            }
+        }
+        if ((r = launch_lsq<T>(a, s))) return r;
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            if ((r = launch_sol_update<T>(ga[gi], groups[gi].n, a, s))) return r;
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            if ((r = launch_true_residual<T>(ga[gi], groups[gi].n, a, s))) return r;
+        return HELM_OK;
+    };
+
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        if ((rc = launch_true_residual<T>(ga[gi], groups[gi].n, a, s))) return rc;
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        if ((rc = launch_zero_done_x(gd[gi], groups[gi].n, a.st, x, s))) return rc;
+    GraphHolder gh;
     const int max_cycles = o.maxit + 2;
     for (int cyc = 0; cyc <= max_cycles; ++cyc) {
-        for (size_t gi = 0; gi < groups.size(); ++gi)
-            if ((rc = launch_true_residual<T>(ga[gi], groups[gi].n, a, s))) return rc;
-        if (first) {
-            for (size_t gi = 0; gi < groups.size(); ++gi)
-                if ((rc = launch_zero_done_x(gd[gi], groups[gi].n, a.st, x, s))) return rc;
-            first = false;
-        }
         HELM_HIP(hipMemcpyAsync(W.hst.data(), a.st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
         HELM_HIP(hipStreamSynchronize(s));
+        ktimer().harvest();
         int nact = 0;
         for (int r = 0; r < nrhs; ++r) nact += W.hst[r].active;
         if (nact == 0) break;
-        for (int j = 0; j < m; ++j) {
-            if ((rc = precond(j))) return rc;
-            for (size_t gi = 0; gi < groups.size(); ++gi)
-                if ((rc = launch_matvec_dot<T>(ga[gi], groups[gi].n, a, j, s))) return rc;
-            for (size_t gi = 0; gi < groups.size(); ++gi)
-                if ((rc = launch_update<T>(ga[gi], groups[gi].n, a, j, 1, s))) return rc;
-            if (!o.no_reorth) {
-                for (size_t gi = 0; gi < groups.size(); ++gi)
-                    if ((rc = launch_dot2<T>(ga[gi], groups[gi].n, a, j, s))) return rc;
-                for (size_t gi = 0; gi < groups.size(); ++gi)
-                    if ((rc = launch_update<T>(ga[gi], groups[gi].n, a, j, 2, s))) return rc;
+        if (o.use_graph) {
+            if (!gh.exec) {
+                ktimer().new_capture();
+                HELM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                int r = cycle_body();
+                hipError_t ce = hipStreamEndCapture(s, &gh.graph);
+                if (r) return r;
+                if (ce != hipSuccess) return fail(HELM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+                HELM_HIP(hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0));
             }
+            HELM_HIP(hipGraphLaunch(gh.exec, s));
+        } else if ((rc = cycle_body())) {
+            return rc;
         }
-        if ((rc = launch_lsq<T>(a, s))) return rc;
-        for (size_t gi = 0; gi < groups.size(); ++gi)
-            if ((rc = launch_sol_update<T>(ga[gi], groups[gi].n, a, s))) return rc;
     }
     if (o.adjoint && (rc = conj_copy<double>(x, x, Ntot, s))) return rc;
     HELM_HIP(hipStreamSynchronize(s));
@@ -332,7 +371,8 @@ int helm_setup(const float* kappa2, const float* gamma, int nz, int nx, double o
             return fail(HELM_EINVAL, "helm_setup: grid too small for %d levels", op->nlev);
         }
         long n = L.n();
-        if ((rc = alloc(&L.k2, n)) || (rc = alloc(&L.g, n)) || (rc = alloc(&L.sl32, n)) || (rc = alloc(&L.sl64, n))) {
+        if ((rc = alloc(&L.k2, n)) || (rc = alloc(&L.g, n)) || (rc = alloc(&L.sl32, n)) || (rc = alloc(&L.sl64, n)) ||
+            (rc = alloc(&L.wd32, n)) || (rc = alloc(&L.wd64, n))) {
             helm_destroy(op);
             return rc;
         }
@@ -381,6 +421,8 @@ void helm_destroy(helm_op_t op) {
         if (L.g) (void)hipFree(L.g);
         if (L.sl32) (void)hipFree(L.sl32);
         if (L.sl64) (void)hipFree(L.sl64);
+        if (L.wd32) (void)hipFree(L.wd32);
+        if (L.wd64) (void)hipFree(L.wd64);
     }
     if (op->roots_dev) (void)hipFree(op->roots_dev);
     if (op->coef32) (void)hipFree(op->coef32);
@@ -462,6 +504,16 @@ int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rh
     if (o.maxit <= 0) o.maxit = 300;
     std::lock_guard<std::mutex> lk(g_mutex);
     hipStream_t s = (hipStream_t)stream;
+    hipStream_t us = s;
+    if (o.use_graph) {
+        s = graph_stream();
+        if (!s) return fail(HELM_EHIP, "helm_solve: could not create the graph stream");
+        hipEvent_t ev;
+        HELM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HELM_HIP(hipEventRecord(ev, us));
+        HELM_HIP(hipStreamWaitEvent(s, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
     if (o.krylov_dtype == HELM_C128)
         return solve_impl<double>(ops, nops, rhs_op, rhs, x, nrhs, tol, o, iters, relres, status, s);
     if (o.krylov_dtype == HELM_C64)

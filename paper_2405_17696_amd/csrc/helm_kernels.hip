@@ -116,8 +116,36 @@ __global__ void k_restrict_field(const float* __restrict__ f, int nz, int nx, fl
     out[(long)I * cx_ + J] = (float)(num / den);
 }
 
+constexpr int POLY_THREADS = 1024;
+constexpr int POLY_NPT = 4;
+constexpr int POLY_LDS_MAX = POLY_THREADS * POLY_NPT;  // 4096 nodes, 2 x 64 KiB of LDS
+template <typename T>
+__global__ void k_poly_lds(const cx<T>* __restrict__ src, cx<T>* __restrict__ out, const c128* __restrict__ sl,
+                           int nz, int nx, Sten<double> sten, const c128* __restrict__ roots, int deg,
+                           const RhsState* __restrict__ st, int rhs0, unsigned long long* wc);
+
+// w / D per node of a level, D = stencil diagonal (with the far-boundary rows) - mass term.
+__global__ void k_level_wdinv(const c128* __restrict__ sl, int nz, int nx, Sten<double> st, double wj,
+                              c64* __restrict__ wd32, c128* __restrict__ wd64) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nz * nx) return;
+    int i = (int)(t / nx), k = (int)(t - (long)i * nx);
+    double dg = (k == nx - 1 ? st.dxl : 2 * st.ax) + (i == nz - 1 ? st.dzl : 2 * st.az);
+    c128 D = mk(dg - sl[t].re, -sl[t].im);
+    c128 w = wj * cinv(D);
+    wd64[t] = w;
+    wd32[t] = ccast<float>(w);
+}
+
 int setup_levels(helm_op* op, const float* k2, const float* g, hipStream_t s) {
     double w2 = op->omega * op->omega;
+    // the single-workgroup coarse polynomial needs 2 x 64 KiB of dynamic LDS
+    static const bool lds_ok =
+        hipFuncSetAttribute((const void*)k_poly_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * POLY_LDS_MAX * (int)sizeof(c128)) == hipSuccess &&
+        hipFuncSetAttribute((const void*)k_poly_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * POLY_LDS_MAX * (int)sizeof(c128)) == hipSuccess;
+    op->poly_lds_ok = lds_ok;
     for (int l = 0; l < op->nlev; ++l) {
         Level& L = op->lv[l];
         if (l > 0) {
@@ -132,6 +160,9 @@ int setup_levels(helm_op* op, const float* k2, const float* g, hipStream_t s) {
         hipLaunchKernelGGL(k_level_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L.k2, L.g, n, w2,
                            op->beta, op->with_gamma, l == 0 ? op->coef32 : nullptr, l == 0 ? op->coef64 : nullptr,
                            L.sl32, L.sl64);
+        HELM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_level_wdinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L.sl64, L.nz, L.nx,
+                           L.sten<double>(), op->jw, L.wd32, L.wd64);
         HELM_CHECK_LAUNCH();
     }
     (void)k2;
@@ -173,7 +204,7 @@ __device__ __forceinline__ NodeSten<T> node_sten(const Sten<T>& s, int i, int k,
 // sits on fine node 2I+1, so a coarse tile I0.. needs fine rows 2I0-1 .. 2I0+33.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_down(const cx<T>* __restrict__ f, const double* __restrict__ fscale,
-                                                 int fstride, const cx<T>* __restrict__ sl, int nz, int nx,
+                                                 int fstride, const cx<T>* __restrict__ wd, int nz, int nx,
                                                  Sten<T> sten, T wj, cx<T>* __restrict__ fc, int cz, int cxn,
                                                  const RhsState* __restrict__ st, int rhs0,
                                                  unsigned long long* wc) {
@@ -199,9 +230,7 @@ __global__ __launch_bounds__(256) void k_mg_down(const cx<T>* __restrict__ f, co
         if (i >= 0 && i < nz && k >= 0 && k < nx) {
             long n = (long)i * nx + k;
             fv = load_f(f, n, scale);
-            NodeSten<T> ns = node_sten(sten, i, k, nz, nx);
-            cx<T> D = mk(ns.dg - sl[n].re, -sl[n].im);
-            ev = wj * (fv * cinv(D));
+            ev = wd[n] * fv;
         }
         fs[pi][pk] = fv;
         e0s[pi][pk] = ev;
@@ -278,7 +307,8 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T>* __restrict__ ec, int i,
 // out = e + w D^-1 (f - P e), e = w D^-1 f + Prol(ec)  (+ addend)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_up(const cx<T>* __restrict__ f, const double* __restrict__ fscale,
-                                               int fstride, const cx<T>* __restrict__ sl, int nz, int nx,
+                                               int fstride, const cx<T>* __restrict__ sl,
+                                               const cx<T>* __restrict__ wd, int nz, int nx,
                                                Sten<T> sten, T wj, const cx<T>* __restrict__ ec, int cz, int cxn,
                                                cx<T>* __restrict__ out, const cx<T>* __restrict__ addend,
                                                const RhsState* __restrict__ st, int rhs0, unsigned long long* wc) {
@@ -302,9 +332,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const cx<T>* __restrict__ f, cons
         cx<T> ev = mk(T(0), T(0));
         if (i >= 0 && i < nz && k >= 0 && k < nx) {
             long n = (long)i * nx + k;
-            NodeSten<T> ns = node_sten(sten, i, k, nz, nx);
-            cx<T> D = mk(ns.dg - sl[n].re, -sl[n].im);
-            ev = wj * (load_f(f, n, scale) * cinv(D)) + prolong_at(ec, i, k, cz, cxn);
+            ev = wd[n] * load_f(f, n, scale) + prolong_at(ec, i, k, cz, cxn);
         }
         es[pi][pk] = ev;
     }
@@ -324,7 +352,7 @@ __global__ __launch_bounds__(256) void k_mg_up(const cx<T>* __restrict__ f, cons
         cx<T> e = es[ti + 1][tk + 1];
         cx<T> res = load_f(f, n, scale) - D * e + ns.cw * es[ti + 1][tk] + ns.ce * es[ti + 1][tk + 2] +
                     ns.cn * es[ti][tk + 1] + ns.cs * es[ti + 2][tk + 1];
-        cx<T> o = e + wj * (res * cinv(D));
+        cx<T> o = e + wd[n] * res;
         if (addend) o = o + addend[n];
         out[n] = o;
     }
@@ -381,10 +409,6 @@ __global__ __launch_bounds__(256) void k_poly_term(const cx<T>* __restrict__ src
 // Whole coarsest-level polynomial in one workgroup per right-hand side, the
 // residual resident in LDS (FP64) and the iterate in registers.  Used when the
 // level has at most POLY_LDS_MAX nodes.
-constexpr int POLY_THREADS = 1024;
-constexpr int POLY_NPT = 4;
-constexpr int POLY_LDS_MAX = POLY_THREADS * POLY_NPT;  // 4096 nodes, 64 KiB of LDS
-
 template <typename T>
 __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restrict__ src, cx<T>* __restrict__ out,
                                                            const c128* __restrict__ sl, int nz, int nx,
@@ -400,13 +424,22 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
     src += (long)rl * N;
     out += (long)rl * N;
     add_work(wc, (unsigned long long)N * 2 * sizeof(cx<T>));
-    extern __shared__ c128 rs[];
+    extern __shared__ c128 lds_poly[];
+    c128* rs = lds_poly;       // residual, N entries
+    c128* ss_ = lds_poly + N;  // mass term minus the stencil diagonal, N entries
     c128 xr[POLY_NPT], rr[POLY_NPT];
+    int ii[POLY_NPT], kk[POLY_NPT];
 #pragma unroll
     for (int q = 0; q < POLY_NPT; ++q) {
         int n = threadIdx.x + q * POLY_THREADS;
         xr[q] = mk(0.0, 0.0);
         rr[q] = n < N ? ccast<double>(src[n]) : mk(0.0, 0.0);
+        ii[q] = n / nx;
+        kk[q] = n - ii[q] * nx;
+        if (n < N) {
+            NodeSten<double> ns = node_sten(sten, ii[q], kk[q], nz, nx);
+            ss_[n] = mk(ns.dg - sl[n].re, -sl[n].im);
+        }
     }
     for (int t = 0; t < deg; ++t) {
         c128 th = roots[t];
@@ -426,12 +459,13 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
         for (int q = 0; q < POLY_NPT; ++q) {
             int n = threadIdx.x + q * POLY_THREADS;
             if (n >= N) continue;
-            int i = n / nx, k = n - i * nx;
+            const int i = ii[q], k = kk[q];
             const c128 zero = mk(0.0, 0.0);
             c128 w = k > 0 ? rs[n - 1] : zero, e = k + 1 < nx ? rs[n + 1] : zero;
-            c128 nn = i > 0 ? rs[n - nx] : zero, ss = i + 1 < nz ? rs[n + nx] : zero;
-            NodeSten<double> ns = node_sten(sten, i, k, nz, nx);
-            c128 pr = ns.dg * rr[q] - ns.cw * w - ns.ce * e - ns.cn * nn - ns.cs * ss - sl[n] * rr[q];
+            c128 nn = i > 0 ? rs[n - nx] : zero, sv = i + 1 < nz ? rs[n + nx] : zero;
+            const bool lx = k == nx - 1, lz = i == nz - 1;
+            double cw = lx ? sten.axl : sten.ax, cn = lz ? sten.azl : sten.az;
+            c128 pr = ss_[n] * rr[q] - cw * w - sten.ax * e - cn * nn - sten.az * sv;
             rr[q] = rr[q] - pr * it;
         }
     }
@@ -448,6 +482,13 @@ static const cx<T>* sl_of(const Level& L) {
         return L.sl32;
     else
         return L.sl64;
+}
+template <typename T>
+static const cx<T>* wd_of(const Level& L) {
+    if constexpr (sizeof(T) == 4)
+        return L.wd32;
+    else
+        return L.wd64;
 }
 
 template <typename T>
@@ -472,7 +513,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             const cx<T>* fin = l == 0 ? f + off0 : w.f[l] + (long)r0 * F.n();
             dim3 grid((C.nx + MG_T - 1) / MG_T, (C.nz + MG_T - 1) / MG_T, nr);
             TIMED_LAUNCH("k_mg_down", s, k_mg_down<T>, grid, dim3(256), 0, s, fin, l == 0 ? fscale : nullptr,
-                         fstride, sl_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.f[l + 1] + (long)r0 * C.n(), C.nz,
+                         fstride, wd_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.f[l + 1] + (long)r0 * C.n(), C.nz,
                          C.nx, st, rhs0 + r0, WORK_COUNTER("k_mg_down"));
             HELM_CHECK_LAUNCH();
         }
@@ -489,11 +530,8 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             c128* xw = w.xw + (long)r0 * n;
             if (l == 0 && (fscale || addend))
                 return fail(HELM_EINVAL, "single-level cycle does not take scaled or offset inputs");
-            static bool lds_attr_ok = hipFuncSetAttribute((const void*)k_poly_lds<T>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                          POLY_LDS_MAX * (int)sizeof(c128)) == hipSuccess;
-            if (n <= POLY_LDS_MAX && op->roots_dev && lds_attr_ok) {
-                size_t lds = (size_t)n * sizeof(c128);
+            if (n <= POLY_LDS_MAX && op->roots_dev && op->poly_lds_ok) {
+                size_t lds = 2 * (size_t)n * sizeof(c128);
                 TIMED_LAUNCH("k_poly_lds", s, k_poly_lds<T>, dim3(nr), dim3(POLY_THREADS), lds, s, src, xdst, C.sl64,
                              C.nz, C.nx, C.sten<double>(), op->roots_dev, deg, st, rhs0 + r0,
                              WORK_COUNTER("k_poly_lds"));
@@ -519,7 +557,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             cx<T>* dst = l == 0 ? out + off0 : w.e[l] + (long)r0 * F.n();
             dim3 grid((F.nx + MG_T - 1) / MG_T, (F.nz + MG_T - 1) / MG_T, nr);
             TIMED_LAUNCH("k_mg_up", s, k_mg_up<T>, grid, dim3(256), 0, s, fin, l == 0 ? fscale : nullptr, fstride,
-                         sl_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.e[l + 1] + (long)r0 * C.n(), C.nz, C.nx, dst,
+                         sl_of<T>(F), wd_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.e[l + 1] + (long)r0 * C.n(), C.nz, C.nx, dst,
                          (l == 0 && addend) ? addend + off0 : nullptr, st, rhs0 + r0, WORK_COUNTER("k_mg_up"));
             HELM_CHECK_LAUNCH();
         }
@@ -569,22 +607,28 @@ __device__ __forceinline__ void block_sum_store(double (*lds)[NW][2], int k, dou
 
 constexpr int NWV = VEC_THREADS / WAVE;  // waves per block
 
-// Last block of a grid: res[k] = sum over blocks b (fixed order within each
-// lane, then a fixed shuffle tree) of part[b*K + k], k < nk.  Wave w handles
-// entries k = w, w + NWV, ...; the result lands in LDS.
-__device__ __forceinline__ void lastblock_reduce(const c128* __restrict__ part, int nblk, int K, int nk,
-                                                 c128* res) {
-    const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
-    for (int k = wv; k < nk; k += NWV) {
+// res[k] = sum over blocks b of part[b*K + k], k < nk, deterministic: thread
+// (slot, k) sums blocks b = slot, slot + nslot, ... in order (all loads of a
+// thread are independent, so they are in flight together), then thread k
+// sums the slots in order.  The result lands in LDS.
+__device__ __forceinline__ void fold_partials(const c128* __restrict__ part, int nblk, int K, int nk, c128* res) {
+    __shared__ c128 slots[VEC_THREADS];
+    const int nslot = VEC_THREADS / nk;
+    const int slot = threadIdx.x / nk, k = threadIdx.x - slot * nk;
+    if (slot < nslot) {
         double re = 0, im = 0;
-        for (int b = ln; b < nblk; b += WAVE) {
+        for (int b = slot; b < nblk; b += nslot) {
             c128 v = part[(long)b * K + k];
             re += v.re;
             im += v.im;
         }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (ln == 0) res[k] = mk(re, im);
+        slots[threadIdx.x] = mk(re, im);
+    }
+    __syncthreads();
+    if (threadIdx.x < nk) {
+        c128 s = mk(0.0, 0.0);
+        for (int sl = 0; sl < nslot; ++sl) s = s + slots[sl * nk + threadIdx.x];
+        res[threadIdx.x] = s;
     }
     __syncthreads();
 }
@@ -822,7 +866,7 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs<T> a, int rhs0, int nb
     const int K = a.m + 2;
     const int nk = mode == RED_DOTS ? j + 2 : mode == RED_DOTS2 ? j + 1 : 1;
     __shared__ c128 red[MAX_RESTART + 2];
-    lastblock_reduce(a.part + (long)r * a.maxblk * K, nblk, K, nk, red);
+    fold_partials(a.part + (long)r * a.maxblk * K, nblk, K, nk, red);
     const long ro = (long)r * (a.m + 1);
     if (mode == RED_DOTS || mode == RED_DOTS2) {
         if (threadIdx.x <= j) a.hcur[ro + threadIdx.x] = a.vscale[ro + threadIdx.x] * red[threadIdx.x];
@@ -870,7 +914,7 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs<T> a, int rhs0, int nb
         c128 hv = a.hcur[ro + i];
         col[i] = pass == 1 ? hv : col[i] + hv;
     }
-    if (pass == 1 && !a.no_reorth && s2 < 0.49 * S.wb2) {
+    if (pass == 1 && a.reorth && s2 < 0.49 * S.wb2) {
         S.need2 = 1;
     } else {
         S.need2 = 0;

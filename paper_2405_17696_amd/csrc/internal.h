@@ -43,6 +43,8 @@ struct Level {
     float* g = nullptr;    // restricted attenuation
     c64* sl32 = nullptr;   // shifted-Laplacian mass term omega^2 m (1 - (g + beta) i)
     c128* sl64 = nullptr;
+    c64* wd32 = nullptr;   // damped-Jacobi factor w / D, D = diagonal of the level operator
+    c128* wd64 = nullptr;
     long n() const { return (long)nz * nx; }
 };
 
@@ -66,6 +68,7 @@ struct helm_op {
     helm::Level lv[helm::MAX_LEVELS];
     std::vector<helm::c128> roots;  // coarsest-level polynomial roots, Leja order
     helm::c128* roots_dev = nullptr;
+    bool poly_lds_ok = false;
     helm::EncCache enc;
     long n() const { return (long)nz * nx; }
 };
@@ -103,7 +106,7 @@ struct GroupArgs {
 // Global solve arguments.
 template <typename T>
 struct SolveArgs {
-    int m, nrhs, maxblk, maxit, conjop, no_reorth;
+    int m, nrhs, maxblk, maxit, conjop, reorth;
     long Ntot;
     double tol;
     cx<T>* V;        // [m+1][Ntot]

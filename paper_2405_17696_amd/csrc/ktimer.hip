@@ -10,7 +10,10 @@ namespace helm {
 namespace {
 struct TimerState {
     std::string name;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;   // eager launches
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> cap;  // launches inside a captured graph
+    double cap_ms = 0;
+    long cap_launches = 0;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     unsigned long long* dcount = nullptr;
@@ -30,18 +33,28 @@ hipEvent_t take_event() {
 
 bool KTimer::armed(const char* name) const { return !g_t.name.empty() && g_t.name == name; }
 unsigned long long* KTimer::counter() const { return g_t.dcount; }
+// Launches inside a stream capture are not timed: the graph replays them.
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
 void KTimer::begin(hipStream_t s) {
+    g_t.pending = nullptr;
+    if (capturing(s)) return;
     g_t.pending = take_event();
     if (g_t.pending) (void)hipEventRecord(g_t.pending, s);
 }
 void KTimer::end(hipStream_t s) {
+    if (!g_t.pending) return;
     hipEvent_t e = take_event();
-    if (g_t.pending && e) {
+    if (e) {
         (void)hipEventRecord(e, s);
         g_t.ev.push_back({g_t.pending, e});
     }
     g_t.pending = nullptr;
 }
+void KTimer::harvest() {}
+void KTimer::new_capture() { g_t.cap.clear(); }
 KTimer& ktimer() {
     static KTimer t;
     return t;
@@ -54,6 +67,9 @@ using namespace helm;
 extern "C" int helm_ktimer_start(const char* kernel) {
     if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_start: device sync failed");
     g_t.ev.clear();
+    g_t.cap.clear();
+    g_t.cap_ms = 0;
+    g_t.cap_launches = 0;
     g_t.used = 0;
     g_t.name = kernel ? kernel : "";
     if (kernel) {
@@ -77,8 +93,8 @@ extern "C" int helm_ktimer_read(int* launches, double* total_ms, double* total_w
     unsigned long long w = 0;
     if (g_t.dcount && hipMemcpy(&w, g_t.dcount, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(HELM_EHIP, "helm_ktimer_read: counter read failed");
-    if (launches) *launches = (int)g_t.ev.size();
-    if (total_ms) *total_ms = ms;
+    if (launches) *launches = (int)(g_t.ev.size() + g_t.cap_launches);
+    if (total_ms) *total_ms = ms + g_t.cap_ms;
     if (total_work) *total_work = (double)w;
     return HELM_OK;
 }

@@ -166,3 +166,27 @@ def test_solve_none_precond(gpu):
     coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
     rel = op.relres(coef, x.cpu().numpy(), b.astype(np.complex128), med.h, med.h)
     assert code == 0 and rel[0] <= 1e-7
+
+
+@pytest.mark.parametrize("reorth", [False, True])
+def test_solve_graph_replay_matches_eager(gpu, reorth):
+    """A restart cycle replayed from a captured graph gives bit-identical
+    iterates to eager launches (the kernels are deterministic); replays are
+    interleaved with eager work on the caller's stream."""
+    n = 64
+    med = medium(n, n, seed=41)
+    H = setup(med)
+    b = to_dev(rand_c((3, n, n), 6).astype(np.complex64))
+    xe, ite, rre, ste, ce = api.helm_solve(H, b, tol=1e-7, precond="mg", maxit=600, reorth=reorth)
+    xe = xe.clone()
+    for rep in range(2):
+        junk = api.helm_matvec(H, b)            # eager work between replays
+        xg, itg, rrg, stg, cg = api.helm_solve(H, b, tol=1e-7, precond="mg", maxit=600, use_graph=True,
+                                               reorth=reorth)
+        torch.cuda.synchronize()
+        assert ce == 0 and cg == 0
+        assert np.array_equal(ite, itg)
+        assert torch.equal(xe, xg)
+    coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
+    rel = op.relres(coef, xg.cpu().numpy(), b.cpu().numpy().astype(np.complex128), med.h, med.h)
+    assert np.all(rel <= 1e-7)
