@@ -122,6 +122,84 @@ int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
 /* Roots of the coarsest-level polynomial, in application order (host, c128 [*n]). */
 int helm_coarse_roots(helm_op_t op, double* roots, int* n);
 
+/* ------------------------------------------------------------------------
+ * Encoder-solver network (Sec. 3.4, 4.1-4.3, Fig. 1).  Architecture: four
+ * levels of widths w[0..3] (default 32, 64, 128, 256); the encoder maps
+ * [omega^2 hx hz m, gamma] to context maps z_0..z_3 (once per operator and
+ * weight version), the solver maps the scaled residual [Re, Im](s r),
+ * s = sqrt(N)/||r||, with z_l concatenated at every level, to hx hz s e.
+ * BF16 activations (NHWC) and weights, FP32 accumulation and master weights.
+ * Grids must have nz, nx divisible by 8.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int widths[4];   /* <= 0: default; multiples of 32 */
+    int down_res;    /* residual blocks per encoder level on the way down; <= 0: 2 */
+} cnn_arch;
+
+/* cnn_create -- network with He-normal weights drawn from Philox-4x32-10 (key = seed). */
+int cnn_create(const cnn_arch* arch, uint64_t seed, cnn_net_t* out);
+void cnn_destroy(cnn_net_t net);
+/* Weights, Adam moments and step count to / from a file (host path). */
+int cnn_save(cnn_net_t net, const char* path);
+int cnn_load(const char* path, cnn_net_t* out);
+/* Flat FP32 parameters, layer by layer, W then b (host buffers of cnn_num_params floats). */
+int cnn_num_params(cnn_net_t net, long* count);
+int cnn_get_params(cnn_net_t net, float* host);
+int cnn_set_params(cnn_net_t net, const float* host);
+int cnn_get_grad(cnn_net_t net, float* host);
+int cnn_zero_grad(cnn_net_t net);
+
+/* Raw network: out = SolverNet(rin; EncoderNet(op)), rin and out FP32
+ * [B][nz][nx][2] (device). */
+int cnn_forward(cnn_net_t net, helm_op_t op, const float* rin, float* out, int B, void* stream);
+/* e = M_net(r) = hx hz net(s r) / s for nrhs c64 vectors (device); Sec. 3.4. */
+int cnn_precond_apply(cnn_net_t net, helm_op_t op, const void* r, void* e, int nrhs, void* stream);
+/* MSE loss of eq. (4.2) on B pairs (r, e) (c64, device) and its gradient,
+ * accumulated into the network's gradient buffer; loss to host (may be NULL). */
+int cnn_loss_grad(cnn_net_t net, helm_op_t op, const void* r, const void* e, int B, double* loss, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the accumulated gradient, which it zeroes. */
+int cnn_adam_step(cnn_net_t net, double lr, void* stream);
+/* Training pairs of eq. (4.3) for samples first .. first+npairs-1: x ~ CN(0,1)
+ * (Philox stream = sample index, key (seed, 0xDA7A)), b = H x, x~ = GMRES with
+ * the V-cycle for k ~ U{1..10} iterations, e = x - x~, r = H e (c64, device). */
+int cnn_make_pairs(helm_op_t op, int first, int npairs, uint64_t seed, void* r, void* e, void* stream);
+/* One data epoch of Alg. 2 on r, e [2*npairs][N] (device): appends the pairs
+ * spawned by the first npairs at index npairs .. 2*npairs-1. */
+int cnn_alg2_epoch(cnn_net_t net, helm_op_t op, void* r, void* e, int npairs, void* stream);
+
+/*
+ * Single-layer hooks (test and tuning): one 3x3 convolution (kind 0: stride 1
+ * or 2, sources x1 [B][H][W][c1] and optionally x2 [B or 1][H][W][c2]
+ * concatenated after x1, weights [cout][3][3][c1+c2]) or one 2x2 up-convolution
+ * (kind 1: weights [2][2][cout][c1]) through the same BF16 MFMA kernels the
+ * networks use.  All arrays are FP32 HOST buffers; inputs are rounded to BF16.
+ * Forward: out = act(conv + b (+ resid)).  Backward: given the forward output y
+ * (for the ReLU mask) and dL/dy, the gradients w.r.t. x1, x2 (per sample), W, b.
+ */
+int cnn_layer_forward(int kind, int stride, int B, int H, int W, int c1, int c2, int bcast2, int cout,
+                      const float* x1, const float* x2, const float* w, const float* b, const float* resid, int relu,
+                      float* out);
+int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2, int bcast2, int cout,
+                       const float* x1, const float* x2, const float* w, const float* y, int relu, const float* gout,
+                       float* gx1, float* gx2, float* gw, float* gb);
+
+typedef struct {
+    int npairs;            /* plain training: pairs generated by eq. (4.3); <= 0: 2000 */
+    int batch;             /* <= 0: 16 */
+    int steps;             /* optimiser steps; <= 0: 200 */
+    double lr;             /* Adam learning rate; <= 0: 1e-4 */
+    int alg2_initial;      /* > 0: Alg. 2 with this initial dataset size */
+    int alg2_data_epochs;  /* Alg. 2: epochs that also generate data */
+    int alg2_epochs;       /* Alg. 2: total epochs */
+    int* steps_done;       /* host output, may be NULL */
+    int* dataset_size;     /* host output, may be NULL */
+} cnn_train_opts;
+
+/* cnn_precond_train -- generate pairs on op's medium and train (Sec. 4.1) or
+ * retrain with Alg. 2 (Sec. 4.2); loss per step to loss_hist (host, steps). */
+int cnn_precond_train(cnn_net_t net, helm_op_t op, const cnn_train_opts* opt, uint64_t seed, float* loss_hist,
+                      void* stream);
+
 /*
  * Diagnostics: time every launch of one named kernel ("k_matvec_dot",
  * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",

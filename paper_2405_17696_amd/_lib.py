@@ -38,6 +38,16 @@ class SolveOpts(C.Structure):
                 ("reorth", C.c_int), ("net", C.c_void_p)]
 
 
+class CnnArch(C.Structure):
+    _fields_ = [("widths", C.c_int * 4), ("down_res", C.c_int)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("npairs", C.c_int), ("batch", C.c_int), ("steps", C.c_int), ("lr", C.c_double),
+                ("alg2_initial", C.c_int), ("alg2_data_epochs", C.c_int), ("alg2_epochs", C.c_int),
+                ("steps_done", C.POINTER(C.c_int)), ("dataset_size", C.POINTER(C.c_int))]
+
+
 _lib = None
 
 # name -> (restype, argtypes); every exported symbol of include/*.h is listed here
@@ -53,6 +63,26 @@ SIGNATURES = {
                              C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
     "helm_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "helm_coarse_roots": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "cnn_create": (C.c_int, [C.POINTER(CnnArch), C.c_uint64, C.POINTER(C.c_void_p)]),
+    "cnn_destroy": (None, [C.c_void_p]),
+    "cnn_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "cnn_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_void_p)]),
+    "cnn_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_long)]),
+    "cnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "cnn_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "cnn_get_grad": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "cnn_zero_grad": (C.c_int, [C.c_void_p]),
+    "cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "cnn_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "cnn_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                C.c_void_p]),
+    "cnn_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "cnn_make_pairs": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cnn_alg2_epoch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "cnn_precond_train": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(TrainOpts), C.c_uint64,
+                                    C.POINTER(C.c_float), C.c_void_p]),
+    "cnn_layer_forward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 5 + [C.c_int, C.c_void_p]),
+    "cnn_layer_backward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 4 + [C.c_int] + [C.c_void_p] * 5),
     "helm_ktimer_start": (C.c_int, [C.c_char_p]),
     "helm_ktimer_read": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "helm_last_error": (C.c_char_p, []),

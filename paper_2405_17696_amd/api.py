@@ -134,3 +134,165 @@ def helm_solve(ops, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float
     L.check(code, soft_ok=True)
     return (x, np.array(it[:], dtype=np.int64), np.array(rr[:], dtype=np.float64),
             np.array(stt[:], dtype=np.int64), code)
+
+
+# ---------------------------------------------------------------- encoder-solver network
+class CnnNet:
+    """Owning wrapper of a cnn_net_t handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    @property
+    def nparams(self):
+        n = C.c_long()
+        L.check(L.load().cnn_num_params(self.handle, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if self.handle:
+            L.load().cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_create(widths=(32, 64, 128, 256), seed=0, down_res=2) -> CnnNet:
+    a = L.CnnArch((C.c_int * 4)(*widths), down_res)
+    out = C.c_void_p()
+    L.check(L.load().cnn_create(C.byref(a), int(seed), C.byref(out)))
+    return CnnNet(out)
+
+
+def cnn_load(path) -> CnnNet:
+    out = C.c_void_p()
+    L.check(L.load().cnn_load(str(path).encode(), C.byref(out)))
+    return CnnNet(out)
+
+
+def cnn_save(net: CnnNet, path):
+    L.check(L.load().cnn_save(net.handle, str(path).encode()))
+
+
+def cnn_get_params(net: CnnNet):
+    import numpy as np
+    a = np.empty(net.nparams, np.float32)
+    L.check(L.load().cnn_get_params(net.handle, a.ctypes.data_as(C.c_void_p)))
+    return a
+
+
+def cnn_set_params(net: CnnNet, theta):
+    import numpy as np
+    a = np.ascontiguousarray(theta, dtype=np.float32)
+    if a.size != net.nparams:
+        raise ValueError(f"expected {net.nparams} parameters, got {a.size}")
+    L.check(L.load().cnn_set_params(net.handle, a.ctypes.data_as(C.c_void_p)))
+
+
+def cnn_get_grad(net: CnnNet):
+    import numpy as np
+    a = np.empty(net.nparams, np.float32)
+    L.check(L.load().cnn_get_grad(net.handle, a.ctypes.data_as(C.c_void_p)))
+    return a
+
+
+def cnn_zero_grad(net: CnnNet):
+    L.check(L.load().cnn_zero_grad(net.handle))
+
+
+def cnn_forward(net: CnnNet, op: HelmOp, rin: torch.Tensor) -> torch.Tensor:
+    """Raw network on scaled inputs rin [B][nz][nx][2] float32 (device)."""
+    if rin.dtype != torch.float32 or rin.shape[1:] != (op.nz, op.nx, 2):
+        raise ValueError("rin must be float32 [B][nz][nx][2]")
+    out = torch.empty_like(rin)
+    L.check(L.load().cnn_forward(net.handle, op.handle, _ptr(rin), _ptr(out), rin.shape[0], _stream()))
+    return out
+
+
+def cnn_precond_apply(net: CnnNet, op: HelmOp, r: torch.Tensor) -> torch.Tensor:
+    if r.dtype != torch.complex64 or r.numel() % op.n:
+        raise ValueError("r must be complex64 [nrhs][nz][nx]")
+    e = torch.empty_like(r)
+    L.check(L.load().cnn_precond_apply(net.handle, op.handle, _ptr(r), _ptr(e), r.numel() // op.n, _stream()))
+    return e
+
+
+def cnn_loss_grad(net: CnnNet, op: HelmOp, r: torch.Tensor, e: torch.Tensor) -> float:
+    if r.dtype != torch.complex64 or e.dtype != torch.complex64 or r.shape != e.shape:
+        raise ValueError("r, e must be complex64 of the same shape")
+    loss = C.c_double()
+    L.check(L.load().cnn_loss_grad(net.handle, op.handle, _ptr(r), _ptr(e), r.numel() // op.n, C.byref(loss),
+                                   _stream()))
+    return loss.value
+
+
+def cnn_adam_step(net: CnnNet, lr=1e-4):
+    L.check(L.load().cnn_adam_step(net.handle, float(lr), _stream()))
+
+
+def cnn_make_pairs(op: HelmOp, first: int, npairs: int, seed: int):
+    r = torch.empty((npairs, op.nz, op.nx), dtype=torch.complex64, device="cuda")
+    e = torch.empty_like(r)
+    L.check(L.load().cnn_make_pairs(op.handle, int(first), int(npairs), int(seed), _ptr(r), _ptr(e), _stream()))
+    return r, e
+
+
+def cnn_alg2_epoch(net: CnnNet, op: HelmOp, r: torch.Tensor, e: torch.Tensor, npairs: int):
+    """r, e hold 2*npairs slots; the pairs spawned by the first npairs fill the rest."""
+    if r.shape[0] < 2 * npairs or e.shape[0] < 2 * npairs:
+        raise ValueError("r, e need room for 2*npairs pairs")
+    L.check(L.load().cnn_alg2_epoch(net.handle, op.handle, _ptr(r), _ptr(e), int(npairs), _stream()))
+
+
+def cnn_precond_train(net: CnnNet, op: HelmOp, npairs=2000, batch=16, steps=200, lr=1e-4, seed=0,
+                      alg2_initial=0, alg2_data_epochs=0, alg2_epochs=0):
+    import numpy as np
+    done = C.c_int()
+    dsz = C.c_int()
+    o = L.TrainOpts(npairs, batch, steps, lr, alg2_initial, alg2_data_epochs, alg2_epochs, C.pointer(done),
+                    C.pointer(dsz))
+    hist = (C.c_float * max(1, steps))()
+    L.check(L.load().cnn_precond_train(net.handle, op.handle, C.byref(o), int(seed), hist, _stream()))
+    return np.array(hist[:done.value], dtype=np.float64), dsz.value
+
+
+def _f32(a):
+    import numpy as np
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _vp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def cnn_layer_forward(kind, stride, x1, w, b, x2=None, bcast2=False, resid=None, relu=True):
+    """One layer through the library kernels; host float arrays, NHWC."""
+    import numpy as np
+    x1, x2, w, b, resid = _f32(x1), _f32(x2), _f32(w), _f32(b), _f32(resid)
+    B, H, Wd, c1 = x1.shape
+    c2 = 0 if x2 is None else x2.shape[-1]
+    cout = w.shape[0] if kind == 0 else w.shape[2]
+    Ho, Wo = ((H + stride - 1) // stride, (Wd + stride - 1) // stride) if kind == 0 else (2 * H, 2 * Wd)
+    out = np.empty((B, Ho, Wo, cout), np.float32)
+    L.check(L.load().cnn_layer_forward(kind, stride, B, H, Wd, c1, c2, int(bcast2), cout, _vp(x1), _vp(x2), _vp(w),
+                                       _vp(b), _vp(resid), int(relu), _vp(out)))
+    return out
+
+
+def cnn_layer_backward(kind, stride, x1, w, y, gout, x2=None, bcast2=False, relu=True):
+    import numpy as np
+    x1, x2, w, y, gout = _f32(x1), _f32(x2), _f32(w), _f32(y), _f32(gout)
+    B, H, Wd, c1 = x1.shape
+    c2 = 0 if x2 is None else x2.shape[-1]
+    cout = w.shape[0] if kind == 0 else w.shape[2]
+    gx1 = np.empty_like(x1)
+    gx2 = None if x2 is None else np.empty((B,) + x2.shape[1:], np.float32)
+    gw = np.empty_like(w)
+    gb = np.empty(cout, np.float32)
+    L.check(L.load().cnn_layer_backward(kind, stride, B, H, Wd, c1, c2, int(bcast2), cout, _vp(x1), _vp(x2), _vp(w),
+                                        _vp(y), int(relu), _vp(gout), _vp(gx1), _vp(gx2), _vp(gw), _vp(gb)))
+    return gx1, gx2, gw, gb

@@ -1,0 +1,75 @@
+// BF16 MFMA convolution kernels of the encoder-solver networks (gfx950).
+#pragma once
+#include "internal.h"
+
+namespace helm {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Row space of every GEMM is a pixel grid (b, y, x) of B x Ho x Wo; how the
+// A operand (pixels x K) is gathered:
+enum GatherMode {
+    G_CONV = 0,   // 3x3 conv, pad 1, stride s: k = tap*C + c, input (s*y+ky-1, s*x+kx-1)
+    G_CONVT = 1,  // transposed 3x3 (data gradient): k = tap*C + c, source (y+1-ky)/s when divisible
+    G_UP = 2,     // 1x1 on the up-conv input: k = c at (y, x)
+    G_UPT = 3,    // up-conv data gradient: k = (2a+d)*C + c at (2y+a, 2x+d)
+};
+// What happens to D[m][n] (+ bias etc.):
+enum EpiMode {
+    E_FWD = 0,    // out[m][n] = act(D + bias[n] (+ resid[m][n])), bf16 (+ optional fp32 copy)
+    E_UPFWD = 1,  // n = (2a+d)*Cout + co -> out[(b, 2y+a, 2x+d)][co] = relu(D + bias[co])
+    E_ACC = 2,    // fp32 accumulate: n < n1 -> acc1[m][n], else acc2[m][n-n1]
+};
+
+
+struct GemmArgs {
+    int gmode;       // GatherMode
+    const bf16* a1;
+    const bf16* a2;
+    int c1, c2;      // channels of the two concatenated sources (c2 = 0: one source)
+    long abs1, abs2; // batch strides (elements) of the sources (0: broadcast)
+    int B, Hi, Wi;   // spatial size of the gathered tensors
+    int Ho, Wo;      // row grid
+    int stride;
+    int K;           // GEMM depth (multiple of 32; padded with zeros past 9*C for small C)
+    int kvalid;      // number of real k's
+    const bf16* w;   // [N][K] bf16
+    int N;
+    int epi;
+    const float* bias;
+    const bf16* resid;
+    int relu;
+    bf16* out;
+    float* outf;
+    float* acc1;
+    float* acc2;
+    int n1;
+    long M;
+    const RhsState* st;  // optional: skip row tiles of samples whose RHS is inactive
+    int rhs0;
+};
+
+struct WgradArgs {
+    const bf16* g;   // masked output gradient, [B][Hg][Wg][Cg]
+    int Hg, Wg, Cg;
+    const bf16* a1;  // forward input sources (as in GemmArgs)
+    const bf16* a2;
+    int c1, c2;
+    long abs1, abs2;
+    int B, Hi, Wi;
+    int stride;
+    int mode;        // G_CONV (conv weights [Cout][9][C]) or G_UP (weights [2][2][Cout][C])
+    int M;           // rows of the weight gradient: Cout (conv) or 4*Cout (up)
+    int N;           // columns: 9*C (conv) or C (up)
+    int Npad;        // N rounded up to the tile
+    long P;          // reduction length (pixels)
+    int pchunk;      // pixels per split
+    float* part;     // [nsplit][M][Npad]
+};
+
+int launch_gemm(const GemmArgs& a, hipStream_t s);
+int launch_wgrad(const WgradArgs& a, int nsplit, hipStream_t s);
+
+}  // namespace helm

@@ -68,7 +68,7 @@ static int conj_copy(const cx<T>* a, cx<T>* b, long n, hipStream_t s) {
 
 // ------------------------------------------------------------------ solve workspace
 struct SolveWork {
-    DevBuf V, Z, st, H, cs, sn, g, vscale, hcur, y, part, bconj;
+    DevBuf V, Z, st, H, cs, sn, g, vscale, hcur, y, part, bconj, maxit;
     DevBuf mg[2 * MAX_LEVELS + 3];
     DevBuf cnn_e0, cnn_res;
     std::vector<RhsState> hst;
@@ -95,7 +95,8 @@ static hipStream_t graph_stream() {
 
 template <typename T>
 static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* xv, int nrhs,
-                      double tol, const helm_solve_opts& o, int* iters, double* relres, int* status, hipStream_t s) {
+                      double tol, const helm_solve_opts& o, int* iters, double* relres, int* status, hipStream_t s,
+                      const int* maxit_rhs_host = nullptr) {
     SolveWork& W = g_work;
     // groups of consecutive RHS sharing an operator
     struct Grp {
@@ -181,6 +182,13 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     }
     if (!o.x0_given) HELM_HIP(hipMemsetAsync(x, 0, sizeof(c128) * Ntot, s));
     HELM_HIP(hipMemsetAsync(W.st.p, 0, sizeof(RhsState) * nrhs, s));
+    const int* maxit_dev = nullptr;
+    if (maxit_rhs_host) {
+        if ((rc = W.maxit.ensure(sizeof(int) * nrhs))) return rc;
+        HELM_HIP(hipMemcpyAsync(W.maxit.p, maxit_rhs_host, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        maxit_dev = (const int*)W.maxit.p;
+    }
+    if ((rc = launch_init_state((RhsState*)W.st.p, nrhs, maxit_dev, o.maxit, s))) return rc;
 
     SolveArgs<T> a;
     a.m = m;
@@ -317,6 +325,23 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
         if (stt == HELM_ENAN) worst = HELM_NOT_CONVERGED;
     }
     return worst;
+}
+
+int solve_fixed_iters(const helm_op* op, const c64* rhs, c128* x, int nrhs, const int* iters, int x0_given,
+                      hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    helm_solve_opts o;
+    memset(&o, 0, sizeof(o));
+    o.precond = HELM_PRECOND_MG;
+    int mx = 1;
+    for (int r = 0; r < nrhs; ++r) mx = std::max(mx, iters[r]);
+    o.restart = std::min(mx, MAX_RESTART);
+    o.maxit = mx;
+    o.x0_given = x0_given;
+    helm_op_t ops[1] = {const_cast<helm_op*>(op)};
+    std::vector<int> ro(nrhs, 0);
+    int rc = solve_impl<float>(ops, 1, ro.data(), rhs, x, nrhs, 1e-300, o, nullptr, nullptr, nullptr, s, iters);
+    return rc == HELM_NOT_CONVERGED ? HELM_OK : rc;
 }
 
 }  // namespace helm

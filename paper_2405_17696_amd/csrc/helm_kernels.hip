@@ -804,7 +804,7 @@ __device__ void givens_finalize(const SolveArgs<T>& a, RhsState& S, int r, int j
     double est = sqrt(norm2(gg[j + 1])) / S.bnorm;
     S.est = est;
     a.vscale[(long)r * (m + 1) + j + 1] = hn > 0 ? 1.0 / hn : 0.0;
-    if (!(hn > 0.0) || !(est > a.tol) || S.iters >= a.maxit) S.cycdone = 1;
+    if (!(hn > 0.0) || !(est > a.tol) || S.iters >= S.maxit) S.cycdone = 1;
 }
 
 // w -= sum_i hcur_i v_i (in place in V[j+1]); partial ||w||^2.
@@ -895,7 +895,7 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs<T> a, int rhs0, int nb
             } else if (S.relres <= a.tol) {
                 S.status = HELM_OK;
                 S.done = 1;
-            } else if (S.iters >= a.maxit) {
+            } else if (S.iters >= S.maxit) {
                 S.status = HELM_NOT_CONVERGED;
                 S.done = 1;
             } else {
@@ -1020,6 +1020,17 @@ __global__ __launch_bounds__(256) void k_residual_vs_e0(GroupArgs<T> g, SolveArg
         pair2<T> o = {sc * v.a - he.a, sc * v.b - he.b};
         st_pair(out + lbase + n0, o);
     }
+}
+
+__global__ void k_init_state(RhsState* st, int nrhs, const int* maxit_rhs, int maxit) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrhs) st[r].maxit = maxit_rhs ? maxit_rhs[r] : maxit;
+}
+
+int launch_init_state(RhsState* st, int nrhs, const int* maxit_rhs, int maxit, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_state, dim3((nrhs + 255) / 256), dim3(256), 0, s, st, nrhs, maxit_rhs, maxit);
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
 }
 
 __global__ void k_zero_done_x(int nblk, long N, long off0, int rhs0, const RhsState* st, c128* x) {

@@ -89,6 +89,7 @@ struct RhsState {
     int need2;       // second Gram-Schmidt pass requested for this step
     int done;        // solve finished
     int cycles;
+    int maxit;       // iteration cap of this RHS
 };
 
 // One group of right-hand sides sharing an operator.
@@ -168,7 +169,14 @@ int launch_scale_copy(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, int 
 template <typename T>
 int launch_residual_vs_e0(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, int j, const cx<T>* e0,
                           cx<T>* out, hipStream_t s);
+int launch_init_state(RhsState* st, int nrhs, const int* maxit_rhs, int maxit, hipStream_t s);
 int launch_zero_done_x(const GroupArgs<double>& g, int ng, const RhsState* st, c128* x, hipStream_t s);
+
+// Fixed-iteration, MG-preconditioned GMRES used by the training-data generation
+// (eq. 4.3) and the light-weight retraining: exactly iters[r] (host) Arnoldi steps
+// for RHS r from x (x0_given) or zero; rhs c64, x c128, one operator.
+int solve_fixed_iters(const helm_op* op, const c64* rhs, c128* x, int nrhs, const int* iters, int x0_given,
+                      hipStream_t s);
 
 // host linear algebra (hostla.cpp)
 std::vector<c128> hessenberg_eigvals(std::vector<c128> A, int n);

@@ -1,0 +1,86 @@
+"""Each layer kind of the networks through the library's BF16 MFMA kernels
+against the oracle's direct convolutions (inputs rounded to BF16 on both
+sides, so the comparison isolates the kernels from the storage precision)."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import relerr
+from oracle import unet as U
+from paper_2405_17696_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+def bf(x):
+    return torch.tensor(np.asarray(x, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def rnd(shape, seed, scale=1.0):
+    return bf(scale * np.random.default_rng(seed).standard_normal(shape))
+
+
+CONV_CASES = [
+    # name, stride, B, H, W, c1, c2, bcast2, cout, relu, resid
+    ("s1", 1, 2, 8, 16, 32, 0, False, 32, True, False),
+    ("s2", 2, 2, 16, 8, 32, 0, False, 64, True, False),
+    ("concat", 1, 2, 8, 8, 32, 32, False, 32, True, False),
+    ("bcast", 1, 3, 8, 8, 64, 64, True, 64, True, False),
+    ("first", 1, 2, 16, 16, 2, 0, False, 32, True, False),
+    ("last", 1, 2, 8, 8, 32, 0, False, 2, False, False),
+    ("resid", 1, 2, 8, 8, 32, 0, False, 32, False, True),
+    ("wide", 2, 1, 8, 8, 128, 0, False, 256, True, False),
+    ("odd", 2, 1, 6, 10, 32, 0, False, 32, True, False),
+]
+
+
+def ref_conv(x1, x2, W, b, stride, bcast2, relu, resid):
+    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])], axis=-1)
+    y = U.conv3x3(x, W, b, stride)
+    if resid is not None:
+        y = y + resid
+    return np.maximum(y, 0) if relu else y
+
+
+@pytest.mark.parametrize("case", CONV_CASES, ids=[c[0] for c in CONV_CASES])
+def test_conv_layer_forward_backward(gpu, case):
+    name, s, B, H, W_, c1, c2, bc, cout, relu, use_resid = case
+    print("layer", name, flush=True)
+    x1 = rnd((B, H, W_, c1), 1)
+    x2 = rnd(((1 if bc else B), H, W_, c2), 2) if c2 else None
+    Wt = rnd((cout, 3, 3, c1 + c2), 3, scale=np.sqrt(2.0 / (9 * (c1 + c2))))
+    b = rnd((cout,), 4, 0.1)
+    Ho, Wo = (H + s - 1) // s, (W_ + s - 1) // s
+    resid = rnd((B, Ho, Wo, cout), 5) if use_resid else None
+    y = api.cnn_layer_forward(0, s, x1, Wt, b, x2=x2, bcast2=bc, resid=resid, relu=relu)
+    yr = ref_conv(x1, x2, Wt, b, s, bc, relu, resid)
+    assert relerr(y, yr) <= 1e-5
+    # backward
+    g = rnd(y.shape, 6)
+    gx1, gx2, gw, gb = api.cnn_layer_backward(0, s, x1, Wt, y, g, x2=x2, bcast2=bc, relu=relu)
+    gm = bf(g * (y > 0)) if relu else g
+    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])], axis=-1)
+    rx, rw, rb = U.conv3x3_backward(x, Wt, gm, s)
+    assert relerr(gw, rw) <= 1e-5
+    assert relerr(gb, rb) <= 1e-5
+    if name != "first" or True:
+        assert relerr(gx1, rx[..., :c1]) <= 1e-5
+    if c2:
+        assert relerr(gx2, rx[..., c1:]) <= 1e-5     # per-sample context gradient
+
+
+@pytest.mark.parametrize("B,H,W_,cin,cout", [(2, 4, 8, 64, 32), (1, 8, 8, 256, 128), (2, 16, 16, 128, 64)])
+def test_upconv_layer_forward_backward(gpu, B, H, W_, cin, cout):
+    x = rnd((B, H, W_, cin), 7)
+    Wt = rnd((2, 2, cout, cin), 8, scale=np.sqrt(2.0 / cin))
+    b = rnd((cout,), 9, 0.1)
+    y = api.cnn_layer_forward(1, 2, x, Wt, b, relu=True)
+    yr = np.maximum(U.upconv(x, Wt, b), 0)
+    assert relerr(y, yr) <= 5e-3                # output stored in BF16
+    g = rnd(y.shape, 10)
+    gx, _, gw, gb = api.cnn_layer_backward(1, 2, x, Wt, y, g, relu=True)
+    gm = bf(g * (y > 0))
+    rx, rw, rb = U.upconv_backward(x, Wt, gm)
+    assert relerr(gx, rx) <= 1e-5
+    assert relerr(gw, rw) <= 1e-5
+    assert relerr(gb, rb) <= 1e-5
