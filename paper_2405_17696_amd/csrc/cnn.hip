@@ -264,15 +264,73 @@ __global__ void k_batch_sum(const float* __restrict__ x, int B, long n, float* _
 }
 
 // Bias gradient partials: part[blk][c] = sum over the block's pixels of gm[p][c].
-__global__ __launch_bounds__(256) void k_bias_part(const bf16* __restrict__ gm, long P, int C, int pchunk,
+// The block reads a contiguous run of the flat [P][C] array in steps of
+// `stride` elements (the largest multiple of lcm(8, C) up to 2048), 8 elements
+// per lane, so a lane's elements keep their channels from step to step; the
+// lane sums are then folded per channel in LDS in a fixed order.
+constexpr int BIAS_STEPS = 32;           // steps per block
+__global__ __launch_bounds__(256) void k_bias_part(const bf16* __restrict__ gm, long n, int C, int stride,
                                                    float* __restrict__ part) {
-    const long p0 = (long)blockIdx.x * pchunk;
-    for (int c = threadIdx.x; c < C; c += 256) {
-        float s = 0;
-        long pe = p0 + pchunk < P ? p0 + pchunk : P;
-        for (long p = p0; p < pe; ++p) s += (float)gm[p * C + c];
-        part[(long)blockIdx.x * C + c] = s;
+    __shared__ float red[2048];
+    __shared__ float red2[256];
+    const int tid = threadIdx.x;
+    const long q0 = (long)blockIdx.x * BIAS_STEPS * stride;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (8 * tid < stride) {
+        for (int it = 0; it < BIAS_STEPS; ++it) {
+            const long q = q0 + (long)it * stride + 8 * tid;
+            if (q + 8 <= n) {
+                bf16x8 v = *reinterpret_cast<const bf16x8*>(gm + q);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[e] += (float)v[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (q + e < n) acc[e] += (float)gm[q + e];
+            }
+        }
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[8 * tid + e] = acc[e];
+    __syncthreads();
+    const int units = stride / C;
+    if (C <= 256) {
+        const int G = 256 / C;           // lanes per channel
+        if (tid < G * C) {
+            const int c = tid % C, g = tid / C;
+            float v = 0;
+            for (int j = g; j < units; j += G) v += red[c + j * C];
+            red2[tid] = v;
+        }
+        __syncthreads();
+        if (tid < C) {
+            float v = 0;
+            for (int g = 0; g < G; ++g) v += red2[g * C + tid];
+            part[(long)blockIdx.x * C + tid] = v;
+        }
+    } else {
+        for (int c = tid; c < C; c += 256) {
+            float v = 0;
+            for (int j = 0; j < units; ++j) v += red[c + j * C];
+            part[(long)blockIdx.x * C + c] = v;
+        }
+    }
+}
+
+// out[c] += sum_q part[q][c]: one block per column, fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void k_fold_cols(const float* __restrict__ part, int nq, int C,
+                                                   float* __restrict__ out) {
+    __shared__ float red[256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    float s = 0;
+    for (int q = tid; q < nq; q += 256) s += part[(long)q * C + c];
+    red[tid] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) out[c] += red[0];
 }
 
 // out[i] (+)= sum_s part[s][i]  (fixed order over the splits)
@@ -569,6 +627,22 @@ static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState*
     return HELM_OK;
 }
 
+// db[c] += sum over pixels of gm[p][c] (gm flat [n / C][C]).
+static int bias_grad(const bf16* gm, long n, int C, float* work, size_t work_elems, float* db, hipStream_t s) {
+    long l = C;
+    while (l % 8) l += C;                // lcm(8, C)
+    if (C <= 0 || l > 2048) return fail(HELM_EINVAL, "cnn: bias gradient of %d channels unsupported", C);
+    const int stride = (int)(2048 / l * l);
+    const int nb = (int)((n + (long)BIAS_STEPS * stride - 1) / ((long)BIAS_STEPS * stride));
+    if ((size_t)nb * C > work_elems) return fail(HELM_EINVAL, "cnn: bias scratch too small");
+    if (nb == 0) return HELM_OK;
+    hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(256), 0, s, gm, n, C, stride, work);
+    HELM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_fold_cols, dim3(C), dim3(256), 0, s, work, nb, C, db);
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
+}
+
 // Backward through a program.  Gradients of tensors are fp32 and must be zero
 // on entry except the seeded output gradient; parameter gradients accumulate
 // into net->grad.  Context gradients (solver -> encoder) go to A.zg (per sample).
@@ -589,15 +663,7 @@ static int run_backward(cnn_net* net, Arena& A, Program& P, hipStream_t s) {
         }
         // bias gradient
         {
-            long Pp = (long)y.B * y.H * y.W;
-            int pchunk = 1024;
-            int nsplit = (int)((Pp + pchunk - 1) / pchunk);
-            if ((size_t)nsplit * y.C > A.work_elems) return fail(HELM_EINVAL, "cnn: bias scratch too small");
-            hipLaunchKernelGGL(k_bias_part, dim3(nsplit), dim3(256), 0, s, gm, Pp, y.C, pchunk, A.work);
-            HELM_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_sum_splits, g1(y.C), dim3(256), 0, s, A.work, nsplit, (long)y.C, (long)y.C, 1,
-                               net->grad + L.boff);
-            HELM_CHECK_LAUNCH();
+            if ((rc = bias_grad(gm, y.n(), y.C, A.work, A.work_elems, net->grad + L.boff, s))) return rc;
         }
         // weight gradient
         {
@@ -1312,7 +1378,8 @@ int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2
     long P = kind == 0 ? (long)B * Ho * Wo : (long)B * H * W;
     int M = kind == 0 ? cout : 4 * cout, N = kind == 0 ? 9 * cin : cin, Npad = (N + 63) / 64 * 64;
     int nsplit = 8;
-    float* part = dev_copy<float>(nullptr, (size_t)nsplit * M * Npad + (size_t)((ny / cout + 1023) / 1024) * cout, k.p);
+    const size_t nbias = (size_t)((ny + BIAS_STEPS * 8 - 1) / (BIAS_STEPS * 8)) * cout;
+    float* part = dev_copy<float>(nullptr, (size_t)nsplit * M * Npad + nbias, k.p);
     if (!wd || !wf || !wt || !x1d || !yd || !gd || !gm || !g1d || !gwd || !part) return fail(HELM_ENOMEM, "buffers");
     if (kind == 0)
         hipLaunchKernelGGL(k_refresh_conv, g1(std::max(nwf, nwt)), dim3(256), 0, nullptr, wd, cout, cin, K, Kt, wf, wt);
@@ -1320,12 +1387,11 @@ int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2
         hipLaunchKernelGGL(k_refresh_up, g1(nw), dim3(256), 0, nullptr, wd, cout, cin, wf, wt);
     hipLaunchKernelGGL(k_relu_bwd, g1(ny), dim3(256), 0, nullptr, gd, yd, ny, relu, gm);
     // bias (reduction over the output pixels)
-    const long Py = (long)B * Ho * Wo;
-    int pchunk = 1024, nb = (int)((Py + pchunk - 1) / pchunk);
     float* bpart = part + (size_t)nsplit * M * Npad;
-    hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(256), 0, nullptr, gm, Py, cout, pchunk, bpart);
     float* gbd = dev_copy<float>(nullptr, cout, k.p);
-    hipLaunchKernelGGL(k_sum_splits, g1(cout), dim3(256), 0, nullptr, bpart, nb, (long)cout, (long)cout, 1, gbd);
+    if (!gbd) return fail(HELM_ENOMEM, "buffers");
+    int rc = bias_grad(gm, ny, cout, bpart, nbias, gbd, nullptr);
+    if (rc) return rc;
     // weights
     WgradArgs wa{};
     wa.g = gm;
@@ -1350,7 +1416,7 @@ int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2
     wa.pchunk = (int)(((P + nsplit - 1) / nsplit + 31) / 32 * 32);
     nsplit = (int)((P + wa.pchunk - 1) / wa.pchunk);
     wa.part = part;
-    int rc = launch_wgrad(wa, nsplit, nullptr);
+    rc = launch_wgrad(wa, nsplit, nullptr);
     if (rc) return rc;
     hipLaunchKernelGGL(k_sum_wsplits, g1(nw), dim3(256), 0, nullptr, part, nsplit, M, N, Npad, gwd);
     // data

@@ -229,6 +229,173 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
     }
 }
 
+// ------------------------------------------------------------------ halo-tiled 3x3 stride-1 convolution
+// A block computes a 16 x 16 pixel tile of one sample for BN output channels.
+// Per chunk of 32 input channels it stages the 18 x 18 input patch and the 9
+// taps of the weights in LDS once and runs all nine taps from there (the
+// implicit-GEMM kernel above re-reads every input pixel nine times through L2).
+// FLIP = 1 runs the data gradient of a stride-1 convolution: taps mirrored,
+// weights [Cin][tap][Cout].
+constexpr int HT = 16;              // tile edge (pixels)
+constexpr int HP = HT + 2;          // patch edge
+constexpr int HC = 32;              // channels per chunk
+constexpr int HLD = HC + 8;         // padded LDS row (bf16)
+
+template <int BN, int FLIP, int EPI>
+__global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long long* wc) {
+    constexpr int WTN = BN / 16;    // MFMA tiles per wave along N
+    __shared__ bf16 Ps[HP * HP][HLD];
+    __shared__ bf16 Ws[9][BN][HLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (a.Wo + HT - 1) / HT, tiles_y = (a.Ho + HT - 1) / HT;
+    int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * HT;
+    t /= tiles_x;
+    const int ty0 = (t % tiles_y) * HT;
+    const int b = t / tiles_y;
+    const int n0 = blockIdx.y * BN;
+    if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) return;
+    const int C = a.c1 + a.c2;
+    if (wc && tid == 0) {
+        int my = a.Ho - ty0 < HT ? a.Ho - ty0 : HT, mx = a.Wo - tx0 < HT ? a.Wo - tx0 : HT;
+        int nr = a.N - n0 < BN ? a.N - n0 : BN;
+        atomicAdd(wc, 2ull * my * mx * nr * (unsigned long long)(9 * C));
+    }
+    f32x4 acc[4][WTN];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    constexpr int PSEG = HP * HP * (HC / 8);        // 1296 16-byte segments of the patch
+    constexpr int WSEG = 9 * BN * (HC / 8);         // weight segments
+    constexpr int PPT = (PSEG + 255) / 256, WPT = (WSEG + 255) / 256;
+    bf16x8 rp[PPT], rw[WPT];
+    auto load = [&](int c0) {
+        const bool s2 = c0 >= a.c1;
+        const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
+        const int cs = s2 ? a.c2 : a.c1, cc = s2 ? c0 - a.c1 : c0;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            int sg = tid + q * 256;
+            if (sg >= PSEG) break;
+            int pix = sg >> 2, sub = sg & 3;
+            int py = pix / HP, px = pix - py * HP;
+            int yi = ty0 + py - 1, xi = tx0 + px - 1;
+            rp[q] = (yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi)
+                        ? ld8(src + ((long)yi * a.Wi + xi) * cs + cc + sub * 8)
+                        : zero8();
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            int sg = tid + q * 256;
+            if (sg >= WSEG) break;
+            int row = sg >> 2, sub = sg & 3;        // row = tap * BN + n
+            int tap = row / BN, n = row - tap * BN;
+            rw[q] = n0 + n < a.N ? ld8(a.w + (long)(n0 + n) * a.K + tap * C + c0 + sub * 8) : zero8();
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            int sg = tid + q * 256;
+            if (sg >= PSEG) break;
+            *reinterpret_cast<bf16x8*>(&Ps[sg >> 2][(sg & 3) * 8]) = rp[q];
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            int sg = tid + q * 256;
+            if (sg >= WSEG) break;
+            int row = sg >> 2;
+            *reinterpret_cast<bf16x8*>(&Ws[row / BN][row % BN][(sg & 3) * 8]) = rw[q];
+        }
+    };
+    const int nchunk = C / HC;
+    load(0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        store();
+        __syncthreads();
+        if (ch + 1 < nchunk) load((ch + 1) * HC);
+        // wave w: tile rows 4w .. 4w+3, each a 16-pixel MFMA row tile
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = FLIP ? 2 - tap / 3 : tap / 3, kx = FLIP ? 2 - tap % 3 : tap % 3;
+            bf16x8 fb[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8*>(&Ws[tap][j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ty = wave * 4 + i;
+                bf16x8 fa = *reinterpret_cast<const bf16x8*>(&Ps[(ty + ky) * HP + (lane & 15) + kx][(lane >> 4) * 8]);
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: acc[i][j][e] = D[pixel (ty = 4w+i, tx = 4(l/16)+e)][n = j*16 + l%16]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ty0 + wave * 4 + i;
+        if (y >= a.Ho) continue;
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            const int n = n0 + j * 16 + (lane & 15);
+            if (n >= a.N) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = tx0 + (lane >> 4) * 4 + e;
+                if (x >= a.Wo) continue;
+                const long m = ((long)b * a.Ho + y) * a.Wo + x;
+                float v = acc[i][j][e];
+                if (EPI == E_FWD) {
+                    v += a.bias[n];
+                    if (a.resid) v += (float)a.resid[m * a.N + n];
+                    if (a.relu) v = v > 0.f ? v : 0.f;
+                    a.out[m * a.N + n] = (bf16)v;
+                    if (a.outf) a.outf[m * a.N + n] = v;
+                } else {
+                    if (n < a.n1)
+                        a.acc1[m * a.n1 + n] += v;
+                    else
+                        a.acc2[m * (a.N - a.n1) + (n - a.n1)] += v;
+                }
+            }
+        }
+    }
+}
+
+// The halo kernel applies when every source has a multiple of 32 channels.
+static bool halo_ok(const GemmArgs& a) {
+    if (!(a.gmode == G_CONV || a.gmode == G_CONVT) || a.stride != 1) return false;
+    if (a.c1 % HC || a.c2 % HC) return false;
+    if (a.gmode == G_CONV && a.epi != E_FWD) return false;
+    if (a.gmode == G_CONVT && a.epi != E_ACC) return false;
+    return a.K >= 9 * (a.c1 + a.c2);
+}
+
+static int launch_halo(const GemmArgs& a, hipStream_t s) {
+    unsigned long long* wc = WORK_COUNTER("k_conv");
+    const int tiles = ((a.Ho + HT - 1) / HT) * ((a.Wo + HT - 1) / HT) * a.B;
+    const bool flip = a.gmode == G_CONVT;
+    if (a.N <= 32) {
+        dim3 grid(tiles, (a.N + 31) / 32);
+        if (flip)
+            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<32, 1, E_ACC>), grid, dim3(256), 0, s, a, wc);
+        else
+            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<32, 0, E_FWD>), grid, dim3(256), 0, s, a, wc);
+    } else {
+        dim3 grid(tiles, (a.N + 63) / 64);
+        if (flip)
+            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<64, 1, E_ACC>), grid, dim3(256), 0, s, a, wc);
+        else
+            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<64, 0, E_FWD>), grid, dim3(256), 0, s, a, wc);
+    }
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
+}
+
 template <int GM>
 static int launch_gemm_mode(const GemmArgs& a, hipStream_t s) {
     unsigned long long* wc = WORK_COUNTER("k_conv");
@@ -246,6 +413,7 @@ static int launch_gemm_mode(const GemmArgs& a, hipStream_t s) {
 int launch_gemm(const GemmArgs& a, hipStream_t s) {
     if (a.K % KC != 0) return fail(HELM_EINVAL, "gemm: K=%d not a multiple of %d", a.K, KC);
     if (a.M <= 0 || a.N <= 0) return HELM_OK;
+    if (halo_ok(a)) return launch_halo(a, s);
     switch (a.gmode) {
         case G_CONV:
             return launch_gemm_mode<G_CONV>(a, s);
