@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rhs", type=int, default=1)
     ap.add_argument("--net", default=None, help="trained network file for the CNN preconditioner")
+    ap.add_argument("--save-net", default=None, help="write the trained network to this file")
+    ap.add_argument("--no-compare", action="store_true", help="skip the graph-replay and MG comparison runs")
     ap.add_argument("--kernel", default=None, help="kernel whose roofline is reported")
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="launch each restart cycle eagerly")
@@ -141,6 +143,8 @@ def main():
                         "ms_per_step_incl_data": 1e3 * tt / max(1, a.train_steps),
                         "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:]))}
             op_t.close()
+        if a.save_net:
+            api.cnn_save(net, a.save_net)
 
     def step(pc):
         op = api.helm_setup(k2, gam, med.omega, med.h)
@@ -174,7 +178,7 @@ def main():
     dt, last, roof = run(precond, a.steps, a.warmup, timer=kernel)
     a.no_graph = not graph_mode
     graph_rate = None
-    if graph_mode:
+    if graph_mode and not a.no_compare:
         dtg, lastg, _ = run(precond, a.steps, 1)
         graph_rate = nrhs * a.steps / dtg
     _, it, rr, st, code = last
@@ -183,7 +187,7 @@ def main():
     value = nrhs * a.steps / dt
     compare = {precond: {"rhs_per_s": value, "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                          "relres_max": float(rr.max()), "rhs_per_s_graph_replay": graph_rate}}
-    if precond != "mg":
+    if precond != "mg" and not a.no_compare:
         dtm, lastm, _ = run("mg", max(1, a.steps // 2), 1)
         compare["mg"] = {"rhs_per_s": nrhs * max(1, a.steps // 2) / dtm, "iters_mean": float(lastm[1].mean())}
         compare["speedup_vs_mg"] = value / compare["mg"]["rhs_per_s"]
@@ -205,7 +209,8 @@ def main():
         cpu = cpu_baseline(med, src, a.cpu_sample_rhs)
     out = {"metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "c64 Krylov / c128 iterate / f64 residual", "data": "synthetic",
+           "dtype": ("bf16 network / " if precond != "mg" else "") + "c64 Krylov / c128 iterate / f64 residual",
+           "data": "synthetic",
            "config": {"workload": "256x256 layered+GRF medium, 10 ppw, 32 surface sources, tol 1e-6",
                       "precond": precond, "restart": a.restart, "global_batch": nrhs, "grid": [256, 256],
                       "parallelism": "single GPU"},
