@@ -1,0 +1,115 @@
+"""Data misfit and its gradient w.r.t. the squared slowness (eq. 3.5, 3.10,
+4.8) -- oracle, test infrastructure only.
+
+Forward model, per frequency w_f and source s: H_f u_fs = g_s with
+g_s = e_src(s) / (hx hz) (a grid delta), H_f = -Lap_h - w_f^2 m (1 - i gamma)
+(eq. 3.1), m = kappa^2.  Data: the wavefield sampled at the receiver nodes,
+R u_fs.
+
+Misfit (eq. 3.5 with an identity covariance):
+    Phi(m) = 1/2 sum_{f,s} || R u_fs - d_fs ||_2^2 .
+
+Gradient by the adjoint state.  Differentiating H_f u = g gives
+du = -H_f^{-1} (dH_f) u with dH_f/dm_k = -w_f^2 (1 - i gamma_k) e_k e_k^T, so
+the Jacobian of the data is J_fs = +w_f^2 R H_f^{-1} diag((1 - i gamma) u_fs)
+(the sign printed with eq. 3.10 is the opposite one; finite differences in the
+tests decide).  With the adjoint field
+    lambda_fs = H_f^{-*} R^T (R u_fs - d_fs)
+            = conj( H_f^{-1} conj(R^T (R u_fs - d_fs)) )    (H_f^T = H_f, eq. 4.8)
+the gradient is
+    dPhi/dm_k = sum_{f,s} Re( conj(lambda_fs[k]) w_f^2 (1 - i gamma_k) u_fs[k] ).
+
+All solves are SuperLU factorisations in complex128.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import operator as op
+
+
+def point_source_rhs(shape, src_idx, hx, hz=None):
+    """g_s = e_src / (hx hz) for every source index (flat node index), [ns][nz][nx]."""
+    hz = hx if hz is None else hz
+    nz, nx = shape
+    g = np.zeros((len(src_idx), nz * nx), np.complex128)
+    for s, k in enumerate(src_idx):
+        g[s, int(k)] = 1.0 / (hx * hz)
+    return g.reshape(len(src_idx), nz, nx)
+
+
+def _solvers(kappa2, gamma, omegas, hx, hz):
+    return [op.DirectSolver(op.assemble_helmholtz(kappa2, gamma, w, hx, hz)) for w in omegas]
+
+
+def wavefields(kappa2, gamma, omegas, hx, src_idx, hz=None):
+    """u[f][s] = H_f^{-1} g_s, complex128 [nf][ns][nz][nx]."""
+    hz = hx if hz is None else hz
+    g = point_source_rhs(kappa2.shape, src_idx, hx, hz)
+    return np.stack([S.solve(g) for S in _solvers(kappa2, gamma, omegas, hx, hz)])
+
+
+def forward_data(kappa2, gamma, omegas, hx, src_idx, rec_idx, hz=None):
+    """d[f][s][r] = u_fs at receiver r."""
+    u = wavefields(kappa2, gamma, omegas, hx, src_idx, hz)
+    nf, ns = u.shape[:2]
+    return np.ascontiguousarray(u.reshape(nf, ns, -1)[:, :, np.asarray(rec_idx)])
+
+
+def misfit(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, hz=None):
+    d = forward_data(kappa2, gamma, omegas, hx, src_idx, rec_idx, hz)
+    res = d - dobs
+    return 0.5 * float(np.sum(np.abs(res) ** 2))
+
+
+def misfit_and_grad(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, hz=None):
+    """Phi and dPhi/dm (float64 [nz][nx]) by one forward and one adjoint solve per (f, s)."""
+    hz = hx if hz is None else hz
+    nz, nx = kappa2.shape
+    n = nz * nx
+    rec = np.asarray(rec_idx)
+    g = point_source_rhs((nz, nx), src_idx, hx, hz).reshape(len(src_idx), n)
+    phi = 0.0
+    grad = np.zeros(n)
+    gam = np.asarray(gamma, np.float64).ravel()
+    for f, (w, S) in enumerate(zip(omegas, _solvers(kappa2, gamma, omegas, hx, hz))):
+        u = S.solve(g)                                   # [ns][n]
+        res = u[:, rec] - dobs[f]                        # [ns][nrec]
+        phi += 0.5 * float(np.sum(np.abs(res) ** 2))
+        src_adj = np.zeros_like(u)
+        src_adj[:, rec] = res                            # R^T res
+        lam = np.conj(S.solve(np.conj(src_adj)))         # H^{-*} R^T res by conjugation
+        grad += np.sum(np.real(np.conj(lam) * (w ** 2) * (1.0 - 1j * gam) * u), axis=0)
+    return phi, grad.reshape(nz, nx)
+
+
+def born(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz=None):
+    """Linearised data J dm = w^2 R H^{-1} ((1 - i gamma) u dm), complex [nf][ns][nrec]."""
+    hz = hx if hz is None else hz
+    nz, nx = kappa2.shape
+    g = point_source_rhs((nz, nx), src_idx, hx, hz).reshape(len(src_idx), -1)
+    gam = np.asarray(gamma, np.float64).ravel()
+    out = []
+    for w, S in zip(omegas, _solvers(kappa2, gamma, omegas, hx, hz)):
+        u = S.solve(g)
+        du = S.solve((w ** 2) * (1.0 - 1j * gam) * u * np.asarray(dm).ravel())
+        out.append(du[:, np.asarray(rec_idx)])
+    return np.stack(out)
+
+
+def born_adjoint(kappa2, gamma, omegas, hx, src_idx, rec_idx, dd, hz=None):
+    """Re(J^H dd) for real model perturbations, float64 [nz][nx]; the adjoint
+    solve here uses SuperLU's conjugate-transpose solve, not the conjugation trick."""
+    hz = hx if hz is None else hz
+    nz, nx = kappa2.shape
+    g = point_source_rhs((nz, nx), src_idx, hx, hz).reshape(len(src_idx), -1)
+    gam = np.asarray(gamma, np.float64).ravel()
+    rec = np.asarray(rec_idx)
+    acc = np.zeros(nz * nx)
+    for f, (w, S) in enumerate(zip(omegas, _solvers(kappa2, gamma, omegas, hx, hz))):
+        u = S.solve(g)
+        q = np.zeros_like(u)
+        q[:, rec] = dd[f]
+        lam = S.solve(q, trans="H")
+        acc += np.sum(np.real(np.conj((w ** 2) * (1.0 - 1j * gam) * u) * lam), axis=0)
+    return acc.reshape(nz, nx)

@@ -1,0 +1,94 @@
+"""Pins of the oracle's misfit gradient (eq. 3.5, 3.10, 4.8) against central
+finite differences of the misfit, a dot-product test between independently
+computed Born and adjoint-Born operators, and special cases (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import fwi
+from paper_2405_17696_amd import synth
+
+
+def small_problem(nz=20, nx=24, seed=3, nsrc=3, nrec=5):
+    rng = np.random.default_rng(seed)
+    c = synth.velocity_grf(nz, nx, rng)
+    # a thin absorbing layer so that gamma != 0 on part of the grid
+    gamma = synth.abl_gamma(nz, nx, width=5)
+    k2 = synth.kappa2_from_velocity(c)
+    h = synth.H_DEFAULT
+    omegas = [synth.omega_for_ppw(float(c.min()), p, h) for p in (12.0, 8.0)]
+    src = 2 * nx + np.array([6, 11, 17])[:nsrc]
+    rec = 3 * nx + np.linspace(5, nx - 6, nrec).astype(int)
+    # observed data from a perturbed model
+    kt = k2 * (1.0 + 0.05 * synth.grf(nz, nx, np.random.default_rng(seed + 1), corr_len=4.0))
+    dobs = fwi.forward_data(kt, gamma, omegas, h, src, rec)
+    return k2, gamma, omegas, h, src, rec, dobs
+
+
+def test_gradient_matches_central_differences():
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    phi, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    assert phi > 0
+    rng = np.random.default_rng(11)
+    for t in range(4):
+        d = rng.standard_normal(k2.shape)
+        eps = 1e-3 * np.abs(k2).max() / np.abs(d).max()
+        fp = fwi.misfit(k2 + eps * d, gamma, omegas, h, src, rec, dobs)
+        fm = fwi.misfit(k2 - eps * d, gamma, omegas, h, src, rec, dobs)
+        fd = (fp - fm) / (2 * eps)
+        assert abs(np.sum(g * d) - fd) <= 1e-5 * abs(fd), (t, np.sum(g * d), fd)
+
+
+def test_gradient_in_absorbing_layer_nodes():
+    # directions supported only where gamma > 0: a dropped (1 - i gamma) fails here
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    _, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    d = np.where(gamma > 0.2, 1.0, 0.0) * np.random.default_rng(5).standard_normal(k2.shape)
+    eps = 1e-3 * np.abs(k2).max()
+    fd = (fwi.misfit(k2 + eps * d, gamma, omegas, h, src, rec, dobs)
+          - fwi.misfit(k2 - eps * d, gamma, omegas, h, src, rec, dobs)) / (2 * eps)
+    assert abs(np.sum(g * d) - fd) <= 1e-5 * abs(fd)
+
+
+def test_single_node_derivative_brute_force():
+    k2, gamma, omegas, h, src, rec, dobs = small_problem(nz=12, nx=14, nsrc=2, nrec=3)
+    _, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    for (i, k) in ((5, 7), (2, 3), (9, 1)):
+        e = np.zeros_like(k2)
+        e[i, k] = 1.0
+        eps = 1e-4 * k2[i, k]
+        fd = (fwi.misfit(k2 + eps * e, gamma, omegas, h, src, rec, dobs)
+              - fwi.misfit(k2 - eps * e, gamma, omegas, h, src, rec, dobs)) / (2 * eps)
+        assert abs(g[i, k] - fd) <= 1e-5 * abs(fd) + 1e-12 * np.abs(g).max()
+
+
+def test_born_dot_product():
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    rng = np.random.default_rng(21)
+    dm = rng.standard_normal(k2.shape)
+    dd = rng.standard_normal(dobs.shape) + 1j * rng.standard_normal(dobs.shape)
+    lhs = np.real(np.vdot(dd, fwi.born(k2, gamma, omegas, h, src, rec, dm)))
+    rhs = np.sum(fwi.born_adjoint(k2, gamma, omegas, h, src, rec, dd) * dm)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_gradient_is_adjoint_born_of_residual():
+    # the gradient's conjugation solve (eq. 4.8) against SuperLU's H^H solve
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    _, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    res = fwi.forward_data(k2, gamma, omegas, h, src, rec) - dobs
+    ga = fwi.born_adjoint(k2, gamma, omegas, h, src, rec, res)
+    assert np.linalg.norm(g - ga) <= 1e-10 * np.linalg.norm(ga)
+
+
+def test_zero_residual_gives_zero_misfit_and_gradient():
+    k2, gamma, omegas, h, src, rec, _ = small_problem()
+    d = fwi.forward_data(k2, gamma, omegas, h, src, rec)
+    phi, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, d)
+    assert phi == pytest.approx(0.0, abs=1e-20)
+    assert np.abs(g).max() == 0.0
+
+
+def test_point_source_scaling():
+    g = fwi.point_source_rhs((4, 5), [7], 0.5, 0.25)
+    assert g.shape == (1, 4, 5)
+    assert g[0, 1, 2] == 8.0 and np.count_nonzero(g) == 1
