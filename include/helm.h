@@ -200,6 +200,36 @@ typedef struct {
 int cnn_precond_train(cnn_net_t net, helm_op_t op, const cnn_train_opts* opt, uint64_t seed, float* loss_hist,
                       void* stream);
 
+/* ------------------------------------------------------------------------
+ * Full-waveform-inversion misfit and gradient (eq. (3.5), (3.10), (4.4)-(4.8)).
+ * ------------------------------------------------------------------------ */
+/*
+ * fwi_misfit_grad -- Phi = 1/2 sum_{f,s} || R u_fs - d_fs ||^2 with
+ * u_fs = H_f^{-1} g_s, and dPhi/dm for the squared slowness m of the media.
+ *   ops[nfreq]: one operator per frequency, all on the same grid and built
+ *     from the same m (the gradient is taken with respect to that m; each
+ *     operator's own omega and gamma enter it);
+ *   src_idx[nsrc], rec_idx[nrec] (host): flat node indices row * nx + col; the
+ *     source of s is the grid delta g_s = e_src / (hx hz); receivers sample the
+ *     wavefield at their nodes and must be distinct;
+ *   dobs: observed data, c64 [nfreq][nsrc][nrec] (device);
+ *   tol, opt: the solver tolerance and options of both solve batches
+ *     (opt->adjoint must be 0; opt->x0_given is ignored);
+ *   misfit (host): Phi, accumulated in FP64;
+ *   grad: dPhi/dm = sum_f w_f^2 sum_s Re(conj(lambda_fs) (1 - i gamma) u_fs),
+ *     lambda_fs = H_f^{-*} R^T (R u_fs - d_fs) by conjugation (eq. (4.8)),
+ *     FP64 accumulation, written as float [nz][nx] (device);
+ *   iters (host, may be NULL): [2][nfreq][nsrc] iterations of the forward
+ *     then the adjoint solves.
+ * All nfreq * nsrc forward solves go into one helm_solve batch, then all
+ * adjoint solves.  Workspace (two c128 and one c64 field per (f, s)) is
+ * allocated and freed inside the call.  Returns HELM_OK, HELM_NOT_CONVERGED if
+ * any solve missed tol (outputs are still written), or a hard error.
+ */
+int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                    const void* dobs, double tol, const helm_solve_opts* opt, double* misfit, float* grad,
+                    int* iters, void* stream);
+
 /*
  * Diagnostics: time every launch of one named kernel ("k_matvec_dot",
  * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",

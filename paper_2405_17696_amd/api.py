@@ -296,3 +296,73 @@ def cnn_layer_backward(kind, stride, x1, w, y, gout, x2=None, bcast2=False, relu
     L.check(L.load().cnn_layer_backward(kind, stride, B, H, Wd, c1, c2, int(bcast2), cout, _vp(x1), _vp(x2), _vp(w),
                                         _vp(y), int(relu), _vp(gout), _vp(gx1), _vp(gx2), _vp(gw), _vp(gb)))
     return gx1, gx2, gw, gb
+
+
+# ---------------------------------------------------------------- FWI misfit and gradient
+def fwi_misfit_grad(ops, src_idx, rec_idx, dobs: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
+                    restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
+                    reorth: bool = False, net=None, grad: torch.Tensor | None = None):
+    """Misfit 1/2 sum |R u - d|^2 over frequencies (one op each) and sources, and its
+    gradient w.r.t. the squared slowness.  src_idx / rec_idx: flat node indices;
+    dobs complex64 [nfreq][nsrc][nrec] on the GPU.  Returns (misfit, grad float32
+    [nz][nx], iters [2][nfreq][nsrc], code)."""
+    import numpy as np
+    lib = L.load()
+    if isinstance(ops, HelmOp):
+        ops = [ops]
+    src = [int(v) for v in np.asarray(src_idx).ravel()]
+    rec = [int(v) for v in np.asarray(rec_idx).ravel()]
+    nf, ns, nr = len(ops), len(src), len(rec)
+    if dobs.dtype != torch.complex64 or tuple(dobs.shape) != (nf, ns, nr):
+        raise ValueError(f"dobs must be complex64 of shape {(nf, ns, nr)}")
+    dobs = dobs.contiguous()
+    if grad is None:
+        grad = torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=dobs.device)
+    if grad.dtype != torch.float32 or grad.numel() != ops[0].n:
+        raise ValueError("grad must be float32 [nz][nx]")
+    handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
+                    L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+    phi = C.c_double()
+    its = (C.c_int * (2 * nf * ns))()
+    code = lib.fwi_misfit_grad(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(dobs),
+                               float(tol), C.byref(o), C.byref(phi), _ptr(grad), its, _stream())
+    L.check(code, soft_ok=True)
+    return phi.value, grad, np.array(its[:], dtype=np.int64).reshape(2, nf, ns), code
+
+
+class FwiMisfit(torch.autograd.Function):
+    """Phi(m) = 1/2 sum_{f,s} |R H_f(m)^{-1} g_s - d_fs|^2 as a differentiable function
+    of the squared slowness m (float32 [nz][nx] on the GPU).  The forward pass runs
+    the forward and adjoint solve batches in the library and keeps dPhi/dm; the
+    backward pass scales it by the incoming gradient.
+
+        phi = FwiMisfit.apply(m, gamma, omegas, h, src_idx, rec_idx, dobs, solve_kw)
+    """
+
+    @staticmethod
+    def forward(ctx, m, gamma, omegas, h, src_idx, rec_idx, dobs, solve_kw=None):
+        kw = dict(solve_kw or {})
+        ops = [helm_setup(m.detach(), gamma, float(w), h) for w in omegas]
+        try:
+            phi, grad, its, code = fwi_misfit_grad(ops, src_idx, rec_idx, dobs, **kw)
+        finally:
+            for o in ops:
+                o.close()
+        ctx.save_for_backward(grad)
+        ctx.mdtype = m.dtype
+        ctx.iters = its
+        ctx.code = code
+        return torch.tensor(phi, dtype=torch.float64, device=m.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return ((gout.to(torch.float64) * grad.to(torch.float64)).to(ctx.mdtype),
+                None, None, None, None, None, None, None)
+
+
+def fwi_misfit(m, gamma, omegas, h, src_idx, rec_idx, dobs, **solve_kw):
+    """Differentiable misfit; see FwiMisfit."""
+    return FwiMisfit.apply(m, gamma, omegas, h, src_idx, rec_idx, dobs, solve_kw)

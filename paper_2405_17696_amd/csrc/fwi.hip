@@ -1,0 +1,181 @@
+// Data misfit of eq. (3.5) (identity covariance) and its gradient with respect
+// to the squared slowness, by one forward and one adjoint solve per
+// (frequency, source); the adjoint solve uses the conjugation identity of
+// eq. (4.8).  The solves are batched through helm_solve: all frequencies and
+// sources of the call go into one ragged launch.
+//
+//   u_fs      = H_f^{-1} g_s,             g_s = e_src(s) / (hx hz)
+//   res_fs    = R u_fs - d_fs              (R: sample at the receiver nodes)
+//   Phi       = 1/2 sum_fs |res_fs|^2
+//   lambda_fs = H_f^{-*} R^T res_fs
+//   dPhi/dm_k = sum_f w_f^2 sum_s Re( conj(lambda_fs[k]) (1 - i gamma_k) u_fs[k] )
+//
+// The last line follows from dH_f/dm_k = -w_f^2 (1 - i gamma_k) e_k e_k^T
+// (eq. 3.1); the Jacobian printed with eq. (3.10) carries the opposite sign.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace helm {
+
+namespace {
+
+__global__ void k_point_sources(const int* __restrict__ src, int ns, int nfs, long N, float amp, c64* __restrict__ rhs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nfs) return;
+    rhs[(long)t * N + src[t % ns]] = c64{amp, 0.f};
+}
+
+// One block per (f, s): residual at the receivers (FP64), the adjoint source
+// R^T res written into the zeroed rhs, and 1/2 |res|^2 folded in a fixed order.
+__global__ __launch_bounds__(256) void k_fwi_residual(const c128* __restrict__ u, const c64* __restrict__ dobs,
+                                                      const int* __restrict__ rec, int nrec, long N,
+                                                      c64* __restrict__ rhs, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int fs = blockIdx.x, tid = threadIdx.x;
+    double acc = 0;
+    for (int r = tid; r < nrec; r += 256) {
+        const c128 v = u[(long)fs * N + rec[r]];
+        const c64 d = dobs[(long)fs * nrec + r];
+        const double re = v.re - (double)d.re, im = v.im - (double)d.im;
+        rhs[(long)fs * N + rec[r]] = c64{(float)re, (float)im};
+        acc += re * re + im * im;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) part[fs] = 0.5 * red[0];
+}
+
+// gacc[k] (+)= w^2 sum_s Re(conj(lam_s[k]) (1 - i gamma_k) u_s[k]) for one frequency.
+__global__ void k_fwi_grad_freq(const c128* __restrict__ u, const c128* __restrict__ lam, const float* __restrict__ gam,
+                                double w2, int ns, long N, int first, double* __restrict__ gacc) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double g = gam[k];
+    double acc = 0;
+    for (int s = 0; s < ns; ++s) {
+        const c128 a = u[(long)s * N + k], l = lam[(long)s * N + k];
+        // (1 - i g) u = (u.re + g u.im) + i (u.im - g u.re)
+        acc += l.re * (a.re + g * a.im) + l.im * (a.im - g * a.re);
+    }
+    gacc[k] = first ? w2 * acc : gacc[k] + w2 * acc;
+}
+
+__global__ void k_to_float(const double* __restrict__ a, long n, float* __restrict__ b) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (float)a[t];
+}
+
+struct Owned {
+    std::vector<void*> p;
+    ~Owned() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    T* get(size_t n) {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return (T*)q;
+    }
+};
+
+}  // namespace
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
+                               int nrec, const void* dobs, double tol, const helm_solve_opts* opt, double* misfit,
+                               float* grad, int* iters, void* stream) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit || !grad)
+        return fail(HELM_EINVAL, "fwi_misfit_grad: bad arguments");
+    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad: tol must be positive");
+    for (int f = 0; f < nfreq; ++f) {
+        if (!ops[f]) return fail(HELM_EINVAL, "fwi_misfit_grad: ops[%d] is NULL", f);
+        const helm_op* a = ops[f];
+        const helm_op* b = ops[0];
+        if (a->nz != b->nz || a->nx != b->nx || a->hx != b->hx || a->hz != b->hz)
+            return fail(HELM_EINVAL, "fwi_misfit_grad: operator %d is on a different grid", f);
+    }
+    const long N = ops[0]->n();
+    for (int i = 0; i < nsrc; ++i)
+        if (src_idx[i] < 0 || src_idx[i] >= N) return fail(HELM_EINVAL, "fwi_misfit_grad: source %d out of range", i);
+    std::vector<int> rs(rec_idx, rec_idx + nrec);
+    std::sort(rs.begin(), rs.end());
+    for (int i = 0; i < nrec; ++i) {
+        if (rs[i] < 0 || rs[i] >= N) return fail(HELM_EINVAL, "fwi_misfit_grad: receiver index out of range");
+        if (i && rs[i] == rs[i - 1]) return fail(HELM_EINVAL, "fwi_misfit_grad: receiver nodes must be distinct");
+    }
+    helm_solve_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    if (o.adjoint) return fail(HELM_EINVAL, "fwi_misfit_grad: opts.adjoint must be 0 (the call runs both solves)");
+    o.x0_given = 0;
+
+    hipStream_t s = (hipStream_t)stream;
+    const int nfs = nfreq * nsrc;
+    Owned own;
+    c64* rhs = own.get<c64>((size_t)nfs * N);
+    c128* u = own.get<c128>((size_t)nfs * N);
+    c128* lam = own.get<c128>((size_t)nfs * N);
+    double* gacc = own.get<double>(N);
+    double* part = own.get<double>(nfs);
+    int* src_d = own.get<int>(nsrc);
+    int* rec_d = own.get<int>(nrec);
+    if (!rhs || !u || !lam || !gacc || !part || !src_d || !rec_d)
+        return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
+    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+
+    std::vector<int> rhs_op(nfs);
+    for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nsrc;
+    std::vector<int> st(nfs), it(nfs);
+
+    // forward solves
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
+    HELM_CHECK_LAUNCH();
+    int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, u, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+    if (rc < 0) return rc;
+    int worst = rc;
+    if (iters) std::copy(it.begin(), it.end(), iters);
+
+    // residuals, misfit, adjoint sources
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    hipLaunchKernelGGL(k_fwi_residual, dim3(nfs), dim3(256), 0, s, u, (const c64*)dobs, rec_d, nrec, N, rhs, part);
+    HELM_CHECK_LAUNCH();
+    std::vector<double> ph(nfs);
+    HELM_HIP(hipMemcpyAsync(ph.data(), part, sizeof(double) * nfs, hipMemcpyDeviceToHost, s));
+
+    // adjoint solves: lambda = H^{-*} R^T res
+    o.adjoint = 1;
+    rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, lam, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    if (iters) std::copy(it.begin(), it.end(), iters + nfs);
+
+    // gradient, frequency by frequency in a fixed order
+    const int nb = (int)((N + 255) / 256);
+    for (int f = 0; f < nfreq; ++f) {
+        const double w2 = ops[f]->omega * ops[f]->omega;
+        hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
+                           lam + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g, w2, nsrc, N, f == 0 ? 1 : 0,
+                           gacc);
+        HELM_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, gacc, N, grad);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipStreamSynchronize(s));
+    double phi = 0;
+    for (int i = 0; i < nfs; ++i) phi += ph[i];
+    *misfit = phi;
+    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}

@@ -1,0 +1,116 @@
+"""FWI misfit and gradient through the library (eq. 3.5, 3.10, 4.8) against the
+oracle's SuperLU-based adjoint-state gradient, central differences of the
+library's own misfit, and the torch.autograd.Function wrapper."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import f32, relerr
+from oracle import fwi
+from paper_2405_17696_amd import _lib as L
+from paper_2405_17696_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(nz=32, nx=40, seed=4, nsrc=3, nrec=6, freqs=(12.0, 8.0)):
+    rng = np.random.default_rng(seed)
+    c = synth.velocity_grf(nz, nx, rng)
+    gamma = f32(synth.abl_gamma(nz, nx, width=8))
+    k2 = f32(synth.kappa2_from_velocity(c))
+    h = synth.H_DEFAULT
+    omegas = [synth.omega_for_ppw(float(c.min()), p, h) for p in freqs]
+    src = 4 * nx + synth.surface_positions(nx, nsrc, width=8)
+    rec = 4 * nx + 1 + synth.surface_positions(nx, nrec, width=8)
+    kt = k2 * (1.0 + 0.05 * synth.grf(nz, nx, np.random.default_rng(seed + 1), corr_len=6.0))
+    dobs = fwi.forward_data(kt, gamma, omegas, h, src, rec)
+    return k2, gamma, omegas, h, src, rec, dobs
+
+
+def gpu_call(k2, gamma, omegas, h, src, rec, dobs, **kw):
+    kd = torch.tensor(k2, dtype=torch.float32, device="cuda")
+    gd = torch.tensor(gamma, dtype=torch.float32, device="cuda")
+    ops = [api.helm_setup(kd, gd, w, h) for w in omegas]
+    d = torch.tensor(dobs, dtype=torch.complex64, device="cuda")
+    phi, g, its, code = api.fwi_misfit_grad(ops, src, rec, d, **kw)
+    for o in ops:
+        o.close()
+    return phi, g.cpu().numpy().astype(np.float64), its, code
+
+
+@pytest.mark.parametrize("kw,tol_g", [
+    (dict(tol=1e-6), 1e-3),                                  # c64 Krylov at the production tolerance
+    (dict(tol=1e-10, krylov_dtype="c128"), 1e-6),            # tight solves
+])
+def test_gradient_matches_oracle(gpu, kw, tol_g):
+    k2, gamma, omegas, h, src, rec, dobs = problem()
+    print("fwi parity", kw, flush=True)
+    # the oracle sees the data as the library stores it (complex64)
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    phi_o, g_o = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    phi, g, its, code = gpu_call(k2, gamma, omegas, h, src, rec, dobs, **kw)
+    assert code == 0
+    assert its.shape == (2, len(omegas), len(src)) and (its > 0).all()
+    assert abs(phi - phi_o) <= 10 * tol_g * phi_o
+    assert relerr(g, g_o) <= tol_g
+
+
+def test_gradient_central_differences_16_directions(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=24, nx=32, nsrc=2, nrec=4)
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    kw = dict(tol=1e-11, krylov_dtype="c128")
+    _, g, _, _ = gpu_call(k2, gamma, omegas, h, src, rec, dobs, **kw)
+    rng = np.random.default_rng(99)
+    for t in range(16):
+        d = rng.standard_normal(k2.shape)
+        eps = 1e-3 * np.abs(k2).max() / np.abs(d).max()
+        kp, km = f32(k2 + eps * d), f32(k2 - eps * d)      # what the library will hold
+        fp, _, _, _ = gpu_call(kp, gamma, omegas, h, src, rec, dobs, **kw)
+        fm, _, _, _ = gpu_call(km, gamma, omegas, h, src, rec, dobs, **kw)
+        fd = fp - fm
+        lin = np.sum(g * (kp - km))
+        print("direction", t, lin, fd, flush=True)
+        assert abs(lin - fd) <= 1e-3 * abs(fd)
+
+
+def test_autograd_function(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=24, nx=32, nsrc=2, nrec=4)
+    d = torch.tensor(dobs, dtype=torch.complex64, device="cuda")
+    m = torch.tensor(k2, dtype=torch.float32, device="cuda", requires_grad=True)
+    gam = torch.tensor(gamma, dtype=torch.float32, device="cuda")
+    phi = api.fwi_misfit(m, gam, omegas, h, src, rec, d, tol=1e-10, krylov_dtype="c128")
+    (3.0 * phi).backward()
+    ops = [api.helm_setup(m.detach(), gam, w, h) for w in omegas]
+    phi2, g2, _, _ = api.fwi_misfit_grad(ops, src, rec, d, tol=1e-10, krylov_dtype="c128")
+    assert phi.item() == pytest.approx(phi2, rel=1e-9)
+    assert relerr(m.grad.cpu().numpy(), 3.0 * g2.cpu().numpy()) <= 1e-6
+
+
+def test_gradient_with_cnn_preconditioner(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=64, nx=64, nsrc=2, nrec=5, freqs=(10.0,))
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    net = api.cnn_create(seed=3)
+    phi_o, g_o = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    phi, g, its, code = gpu_call(k2, gamma, omegas, h, src, rec, dobs, tol=1e-6, precond="cnn_vu", net=net,
+                                 restart=10)
+    assert code == 0
+    assert abs(phi - phi_o) <= 1e-2 * phi_o
+    assert relerr(g, g_o) <= 1e-3
+
+
+def test_zero_residual(gpu):
+    k2, gamma, omegas, h, src, rec, _ = problem()
+    d0 = fwi.forward_data(k2, gamma, omegas, h, src, rec).astype(np.complex64).astype(np.complex128)
+    phi0, g0, _, _ = gpu_call(k2, gamma, omegas, h, src, rec, d0, tol=1e-10, krylov_dtype="c128")
+    _, g1, _, _ = gpu_call(k2, gamma, omegas, h, src, rec, problem()[-1], tol=1e-10, krylov_dtype="c128")
+    dnorm2 = 0.5 * np.sum(np.abs(d0) ** 2)
+    assert phi0 <= 1e-12 * dnorm2
+    assert np.abs(g0).max() <= 1e-4 * np.abs(g1).max()
+
+
+def test_bad_arguments(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem()
+    with pytest.raises(L.HelmError):        # duplicate receivers
+        gpu_call(k2, gamma, omegas, h, src, np.array([rec[0], rec[0], *rec[2:]]), dobs)
+    with pytest.raises(L.HelmError):        # index out of range
+        gpu_call(k2, gamma, omegas, h, np.array([k2.size]), rec, dobs[:, :1])
