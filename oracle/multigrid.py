@@ -171,6 +171,7 @@ def harmonic_ritz(L, degree):
     GMRES residual polynomial for that start vector."""
     shape = L.coef.shape
     n = L.coef.size
+    degree = min(degree, n)          # the Krylov space has at most n dimensions
     V = np.zeros((degree + 1, n), np.complex128)
     Hh = np.zeros((degree + 1, degree), np.complex128)
     v0 = philox.complex_uniform(n, COARSE_KEY)
@@ -178,11 +179,12 @@ def harmonic_ritz(L, degree):
     k = degree
     for j in range(degree):
         w = L.apply(V[j].reshape(shape)).ravel()
+        w_norm = np.linalg.norm(w)
         for i in range(j + 1):
             Hh[i, j] = np.vdot(V[i], w)
             w = w - Hh[i, j] * V[i]
         Hh[j + 1, j] = np.linalg.norm(w)
-        if Hh[j + 1, j] == 0.0:
+        if Hh[j + 1, j] <= 1e-12 * w_norm:      # invariant subspace reached
             k = j + 1
             break
         V[j + 1] = w / Hh[j + 1, j]
