@@ -114,6 +114,8 @@ std::vector<c128> leja_order(const std::vector<c128>& th) {
 std::vector<c128> coarse_roots_host(const Level& L, int degree) {
     const int nz = L.nz, nx = L.nx;
     const long n = L.n();
+    // a Krylov space of the level has at most n dimensions
+    if (degree > n) degree = (int)n;
     std::vector<c128> slh(n);
     if (hipMemcpy(slh.data(), L.sl64, n * sizeof(c128), hipMemcpyDeviceToHost) != hipSuccess) return {};
     const Sten<double> st = L.sten<double>();
@@ -145,6 +147,9 @@ std::vector<c128> coarse_roots_host(const Level& L, int degree) {
     std::vector<zc> w(n);
     for (int j = 0; j < degree; ++j) {
         apply(V[j], w);
+        double wn0 = 0;
+        for (long p = 0; p < n; ++p) wn0 += std::norm(w[p]);
+        wn0 = std::sqrt(wn0);
         for (int i = 0; i <= j; ++i) {
             zc h = 0;
             for (long p = 0; p < n; ++p) h += std::conj(V[i][p]) * w[p];
@@ -155,7 +160,7 @@ std::vector<c128> coarse_roots_host(const Level& L, int degree) {
         for (long p = 0; p < n; ++p) hn += std::norm(w[p]);
         hn = std::sqrt(hn);
         Hh[(j + 1) * degree + j] = hn;
-        if (hn == 0) {
+        if (hn <= 1e-12 * wn0) {   // L V_j lies in the span: the space is invariant
             k = j + 1;
             break;
         }
