@@ -37,6 +37,11 @@ struct LayerDesc {
     long wb_off;      // offset of the forward bf16 weights [N][K]
     long wt_off;      // offset of the data-gradient bf16 weights [Cin][Kt]
     int Kt;           // data-gradient GEMM depth
+    // solver context convolutions conv(concat(h, z)): the weights split into
+    // the h part [N][Kh] and the z part [N][Kz] (inference evaluates the z part
+    // once per encoder pass)
+    int ctx = 0, ch = 0, Kh = 0, Kz = 0;
+    long wh_off = 0, wz_off = 0;
 };
 
 static int pad32(int k) { return (k + 31) / 32 * 32; }
@@ -67,12 +72,14 @@ namespace helm {
 // ------------------------------------------------------------------ layer table
 static void build_layers(cnn_net* n) {
     const int* w = n->widths;
-    auto add = [&](int kind, int cin, int cout, int stride) {
+    auto add = [&](int kind, int cin, int cout, int stride, int ctx = 0) {
         LayerDesc L{};
         L.kind = kind;
         L.cin = cin;
         L.cout = cout;
         L.stride = stride;
+        L.ctx = ctx;
+        L.ch = ctx ? cin - cout : 0;   // h has cout channels, z the rest
         n->layers.push_back(L);
     };
     add(L_CONV, 2, w[0], 1);
@@ -88,11 +95,11 @@ static void build_layers(cnn_net* n) {
     }
     n->n_enc = (int)n->layers.size();
     add(L_CONV, 2, w[0], 1);
-    add(L_CONV, 2 * w[0], w[0], 1);
+    add(L_CONV, 2 * w[0], w[0], 1, 1);
     add(L_CONV, w[0], w[0], 1), add(L_CONV, w[0], w[0], 1);
     for (int l = 1; l < 4; ++l) {
         add(L_CONV, w[l - 1], w[l], 2);
-        add(L_CONV, 2 * w[l], w[l], 1);
+        add(L_CONV, 2 * w[l], w[l], 1, 1);
         add(L_CONV, w[l], w[l], 1), add(L_CONV, w[l], w[l], 1);
     }
     for (int l = 2; l >= 0; --l) {
@@ -115,6 +122,14 @@ static void build_layers(cnn_net* n) {
             ob += (long)L.cout * L.K;
             L.wt_off = ob;
             ob += (long)L.cin * L.Kt;
+            if (L.ctx) {
+                L.Kh = pad32(9 * L.ch);
+                L.Kz = pad32(9 * (L.cin - L.ch));
+                L.wh_off = ob;
+                ob += (long)L.cout * L.Kh;
+                L.wz_off = ob;
+                ob += (long)L.cout * L.Kz;
+            }
         } else {
             L.K = L.cin;
             L.Kt = 4 * L.cout;
@@ -148,6 +163,26 @@ __global__ void k_refresh_conv(const float* __restrict__ W, int cout, int cin, i
             v = (bf16)W[((long)co * 9 + tap) * cin + ci];
         }
         wt[t] = v;
+    }
+}
+
+// Split copies of a context convolution: wh[co][tap*ch + c] = W[co][tap][c],
+// wz[co][tap*cz + c] = W[co][tap][ch + c] (zero padded to Kh, Kz).
+__global__ void k_refresh_split(const float* __restrict__ W, int cout, int ch, int cz, int Kh, int Kz,
+                                bf16* __restrict__ wh, bf16* __restrict__ wz) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int cin = ch + cz;
+    if (t < (long)cout * Kh) {
+        const int co = (int)(t / Kh), k = (int)(t - (long)co * Kh);
+        bf16 v = (bf16)0.0f;
+        if (k < 9 * ch) v = (bf16)W[((long)co * 9 + k / ch) * cin + k % ch];
+        wh[t] = v;
+    }
+    if (t < (long)cout * Kz) {
+        const int co = (int)(t / Kz), k = (int)(t - (long)co * Kz);
+        bf16 v = (bf16)0.0f;
+        if (k < 9 * cz) v = (bf16)W[((long)co * 9 + k / cz) * cin + ch + k % cz];
+        wz[t] = v;
     }
 }
 
@@ -456,6 +491,7 @@ struct Arena {
     float* work = nullptr;   // wgrad / bias partials
     size_t work_elems = 0;
     float* zg[4] = {nullptr, nullptr, nullptr, nullptr};  // per-sample context gradients
+    float* zc[4] = {nullptr, nullptr, nullptr, nullptr};  // inference: z part (+ bias) of the context convs
     bf16* gm = nullptr;      // masked output gradient (bf16), largest tensor
     ~Arena() {
         for (void* p : allocs) (void)hipFree(p);
@@ -549,6 +585,12 @@ static int alloc_arena(const cnn_net* net, Arena& A) {
         }
     }
     if ((rc = dalloc(A, (void**)&A.sol.outf, sizeof(float) * A.sol.t[A.sol.output].n()))) return rc;
+    if (!A.train) {
+        for (int l = 0; l < 4; ++l) {
+            const Tens& z = A.enc.t[A.enc.z[l]];
+            if ((rc = dalloc(A, (void**)&A.zc[l], sizeof(float) * (long)z.H * z.W * z.C))) return rc;
+        }
+    }
     if (A.train) {
         for (int l = 0; l < 4; ++l) {
             const Tens& z = A.enc.t[A.enc.z[l]];
@@ -596,11 +638,18 @@ static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState*
         g.out = y.d;
         g.st = (&P == &A.sol) ? st : nullptr;
         g.rhs0 = rhs0;
-        if (op.in2 != -1) {
+        const bool split = L.ctx && !A.train && op.bcast2 && op.in2 <= -2;
+        if (op.in2 != -1 && !split) {
             const Tens& x2 = tens_of(A, P, op.in2);
             g.a2 = x2.d;
             g.c2 = x2.C;
             g.abs2 = op.bcast2 ? 0 : x2.bs();
+        }
+        if (split) {
+            // conv(concat(h, z)) = conv_h(h) + [conv_z(z) + b], the bracket precomputed per encoder pass
+            g.w = net->wb + L.wh_off;
+            g.K = L.Kh;
+            g.bmap = A.zc[-op.in2 - 2];
         }
         if (op.kind == OP_CONV) {
             g.gmode = G_CONV;
@@ -786,6 +835,12 @@ static int refresh_weights(cnn_net* net, hipStream_t s) {
             long n = std::max<long>((long)L.cout * L.K, (long)L.cin * L.Kt);
             hipLaunchKernelGGL(k_refresh_conv, g1(n), dim3(256), 0, s, net->master + L.woff, L.cout, L.cin, L.K, L.Kt,
                                net->wb + L.wb_off, net->wb + L.wt_off);
+            if (L.ctx) {
+                HELM_CHECK_LAUNCH();
+                long ns = (long)L.cout * std::max(L.Kh, L.Kz);
+                hipLaunchKernelGGL(k_refresh_split, g1(ns), dim3(256), 0, s, net->master + L.woff, L.cout, L.ch,
+                                   L.cin - L.ch, L.Kh, L.Kz, net->wb + L.wh_off, net->wb + L.wz_off);
+            }
         } else {
             hipLaunchKernelGGL(k_refresh_up, g1(4L * L.cout * L.cin), dim3(256), 0, s, net->master + L.woff, L.cout,
                                L.cin, net->wb + L.wb_off, net->wb + L.wt_off);
@@ -808,7 +863,38 @@ static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s) {
     hipLaunchKernelGGL(k_enc_input, g1(n), dim3(256), 0, s, op->lv[0].k2, op->lv[0].g, n, sc,
                        A.enc.t[A.enc.input].d);
     HELM_CHECK_LAUNCH();
-    return run_forward(net, A, A.enc, nullptr, 0, s);
+    int rc = run_forward(net, A, A.enc, nullptr, 0, s);
+    if (rc || A.train) return rc;
+    // z parts of the solver's context convolutions (batch independent)
+    for (const Op& o : A.sol.ops) {
+        const LayerDesc& L = net->layers[o.layer];
+        if (!L.ctx || o.in2 > -2) continue;
+        const int l = -o.in2 - 2;
+        const Tens& z = A.enc.t[A.enc.z[l]];
+        GemmArgs g{};
+        g.gmode = G_CONV;
+        g.a1 = z.d;
+        g.c1 = z.C;
+        g.abs1 = z.bs();
+        g.B = 1;
+        g.Hi = z.H;
+        g.Wi = z.W;
+        g.Ho = z.H;
+        g.Wo = z.W;
+        g.stride = 1;
+        g.w = net->wb + L.wz_off;
+        g.K = L.Kz;
+        g.kvalid = 9 * z.C;
+        g.N = L.cout;
+        g.epi = E_FWD;
+        g.bias = net->master + L.boff;
+        g.relu = 0;
+        g.out = nullptr;
+        g.outf = A.zc[l];
+        g.M = (long)z.H * z.W;
+        if ((rc = launch_gemm(g, s))) return rc;
+    }
+    return HELM_OK;
 }
 
 // Inference arenas keep the encoder context of the last (op, version) pair.

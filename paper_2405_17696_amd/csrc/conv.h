@@ -18,7 +18,7 @@ enum GatherMode {
 };
 // What happens to D[m][n] (+ bias etc.):
 enum EpiMode {
-    E_FWD = 0,    // out[m][n] = act(D + bias[n] (+ resid[m][n])), bf16 (+ optional fp32 copy)
+    E_FWD = 0,    // out[m][n] = act(D + bias[n] (+ resid[m][n])), bf16 (+ optional fp32 copy); out may be null
     E_UPFWD = 1,  // n = (2a+d)*Cout + co -> out[(b, 2y+a, 2x+d)][co] = relu(D + bias[co])
     E_ACC = 2,    // fp32 accumulate: n < n1 -> acc1[m][n], else acc2[m][n-n1]
 };
@@ -49,6 +49,7 @@ struct GemmArgs {
     long M;
     const RhsState* st;  // optional: skip row tiles of samples whose RHS is inactive
     int rhs0;
+    const float* bmap;   // E_FWD: fp32 [Ho][Wo][N] added instead of bias (same for every sample)
 };
 
 struct WgradArgs {

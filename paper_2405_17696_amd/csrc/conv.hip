@@ -6,7 +6,11 @@
 // gradients with the reduction over pixels split across workgroups.
 //
 // MFMA v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+7],
-// B[8(l/16)..+7][l%16] and D[4(l/16)+i][l%16], i = 0..3.
+// B[8(l/16)..+7][l%16] and D[4(l/16)+i][l%16], i = 0..3.  Every kernel here
+// passes the weights as A and the pixels as B, so that the accumulators of a
+// lane are four consecutive output channels of one pixel (vector stores).
+#include <algorithm>
+
 #include "conv.h"
 
 namespace helm {
@@ -98,6 +102,7 @@ __device__ __forceinline__ bf16x8 gather8(const GemmArgs& a, long m, int k0) {
     }
 }
 
+typedef __bf16 bf16x4g __attribute__((ext_vector_type(4)));
 constexpr int KC = 32;      // k per chunk
 constexpr int LDS_K = 40;   // padded row length (bf16) of the LDS tiles
 
@@ -185,44 +190,107 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
 #pragma unroll
         for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j], fa[i], acc[i][j], 0, 0, 0);
         if (kc + 1 < nchunk) {
             store_chunk(buf ^ 1);
             __syncthreads();
         }
     }
 
-    // epilogue
+    // epilogue: the MFMA ran with the weights as A, so acc[i][j][e] holds
+    // D[m = row tile i + l%16][n = column tile j + 4 (l/16) + e]: four consecutive
+    // output channels of one pixel per lane
 #pragma unroll
     for (int i = 0; i < WTM; ++i) {
+        const long m = m0 + wm * (BM / WGM) + i * 16 + (lane & 15);
+        if (m >= a.M) continue;
 #pragma unroll
         for (int j = 0; j < WTN; ++j) {
-            const int n = n0 + wn * (BN / WGN) + j * 16 + (lane & 15);
+            const int n = n0 + wn * (BN / WGN) + j * 16 + (lane >> 4) * 4;
             if (n >= a.N) continue;
+            f32x4 v = acc[i][j];
+            if (a.epi == E_FWD) {
+                const long pm = m % ((long)a.Ho * a.Wo);     // pixel within the sample (bmap index)
+                if ((a.N & 3) == 0) {
+                    const float4 bb = a.bmap ? *reinterpret_cast<const float4*>(a.bmap + pm * a.N + n)
+                                             : *reinterpret_cast<const float4*>(a.bias + n);
+                    v[0] += bb.x;
+                    v[1] += bb.y;
+                    v[2] += bb.z;
+                    v[3] += bb.w;
+                    if (a.resid) {
+                        const bf16x4g r = *reinterpret_cast<const bf16x4g*>(a.resid + m * a.N + n);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const long m = m0 + wm * (BM / WGM) + i * 16 + (lane >> 4) * 4 + e;
-                if (m >= a.M) continue;
-                float v = acc[i][j][e];
-                if (a.epi == E_FWD) {
-                    v += a.bias[n];
-                    if (a.resid) v += (float)a.resid[m * a.N + n];
-                    if (a.relu) v = v > 0.f ? v : 0.f;
-                    a.out[m * a.N + n] = (bf16)v;
-                    if (a.outf) a.outf[m * a.N + n] = v;
-                } else if (a.epi == E_UPFWD) {
-                    const int cout = a.N >> 2;
+                        for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
+                    }
+                    if (a.relu)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                    if (a.out) {
+                        bf16x4g o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+                        *reinterpret_cast<bf16x4g*>(a.out + m * a.N + n) = o;
+                    }
+                    if (a.outf) *reinterpret_cast<f32x4*>(a.outf + m * a.N + n) = v;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (n + e >= a.N) break;
+                        float w = v[e] + (a.bmap ? a.bmap[pm * a.N + n + e] : a.bias[n + e]);
+                        if (a.resid) w += (float)a.resid[m * a.N + n + e];
+                        if (a.relu) w = w > 0.f ? w : 0.f;
+                        if (a.out) a.out[m * a.N + n + e] = (bf16)w;
+                        if (a.outf) a.outf[m * a.N + n + e] = w;
+                    }
+                }
+            } else if (a.epi == E_UPFWD) {
+                const int cout = a.N >> 2;
+                const Pix p = pix_of(m, a.Ho, a.Wo);
+                if ((cout & 3) == 0) {
                     const int ad = n / cout, co = n - ad * cout;
-                    const Pix p = pix_of(m, a.Ho, a.Wo);
-                    long o = (((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) * cout + co;
-                    v += a.bias[co];
-                    if (a.relu) v = v > 0.f ? v : 0.f;
-                    a.out[o] = (bf16)v;
-                } else {  // E_ACC
-                    if (n < a.n1)
-                        a.acc1[m * a.n1 + n] += v;
-                    else
-                        a.acc2[m * (a.N - a.n1) + (n - a.n1)] += v;
+                    const long o = (((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) *
+                                       cout + co;
+                    const float4 bb = *reinterpret_cast<const float4*>(a.bias + co);
+                    v[0] += bb.x;
+                    v[1] += bb.y;
+                    v[2] += bb.z;
+                    v[3] += bb.w;
+                    bf16x4g ov;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ov[e] = (bf16)(a.relu ? (v[e] > 0.f ? v[e] : 0.f) : v[e]);
+                    *reinterpret_cast<bf16x4g*>(a.out + o) = ov;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ne = n + e;
+                        if (ne >= a.N) break;
+                        const int ad = ne / cout, co = ne - ad * cout;
+                        const long o =
+                            (((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) * cout + co;
+                        float w = v[e] + a.bias[co];
+                        if (a.relu) w = w > 0.f ? w : 0.f;
+                        a.out[o] = (bf16)w;
+                    }
+                }
+            } else {  // E_ACC
+                const int n2 = a.N - a.n1;
+                if (n + 4 <= a.n1 && (a.n1 & 3) == 0) {
+                    f32x4* q = reinterpret_cast<f32x4*>(a.acc1 + m * a.n1 + n);
+                    *q = *q + v;
+                } else if (n >= a.n1 && n + 4 <= a.N && (n2 & 3) == 0 && ((n - a.n1) & 3) == 0) {
+                    f32x4* q = reinterpret_cast<f32x4*>(a.acc2 + m * n2 + (n - a.n1));
+                    *q = *q + v;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ne = n + e;
+                        if (ne >= a.N) break;
+                        if (ne < a.n1)
+                            a.acc1[m * a.n1 + ne] += v[e];
+                        else
+                            a.acc2[m * n2 + (ne - a.n1)] += v[e];
+                    }
                 }
             }
         }
@@ -230,20 +298,219 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
 }
 
 // ------------------------------------------------------------------ halo-tiled 3x3 stride-1 convolution
-// A block computes a 16 x 16 pixel tile of one sample for BN output channels.
-// Per chunk of 32 input channels it stages the 18 x 18 input patch and the 9
+// A block computes 16 x 16 output pixels of one sample for BN output channels.
+// Per chunk of 32 input channels it stages the 18 x 18 input patch and the nine
 // taps of the weights in LDS once and runs all nine taps from there (the
 // implicit-GEMM kernel above re-reads every input pixel nine times through L2).
+// Wave w owns output rows 4w .. 4w+3; for a fixed kx the six patch rows
+// 4w .. 4w+5 each feed up to three (row, ky) products, so every pixel
+// fragment is read from LDS once per kx instead of once per tap.
+// The MFMA takes the weights as A and the pixels as B, so a lane ends with four
+// consecutive output channels of one pixel and stores them as one 8-byte vector.
 // FLIP = 1 runs the data gradient of a stride-1 convolution: taps mirrored,
 // weights [Cin][tap][Cout].
 constexpr int HT = 16;              // tile edge (pixels)
 constexpr int HP = HT + 2;          // patch edge
 constexpr int HC = 32;              // channels per chunk
 constexpr int HLD = HC + 8;         // padded LDS row (bf16)
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+template <int BN>
+struct HaloStage {
+    static constexpr int PSEG = HP * HP * (HC / 8);   // 16-byte segments of the patch
+    static constexpr int WSEG = 9 * BN * (HC / 8);    // and of the weights
+    static constexpr int PPT = (PSEG + 255) / 256, WPT = (WSEG + 255) / 256;
+    bf16x8 rp[PPT], rw[WPT];
+
+    __device__ __forceinline__ void load(const GemmArgs& a, int tid, int b, int ty0, int tx0, int n0, int c0,
+                                         bool weights) {
+        const bool s2 = c0 >= a.c1;
+        const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
+        const int cs = s2 ? a.c2 : a.c1, cc = s2 ? c0 - a.c1 : c0;
+        const int C = a.c1 + a.c2;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg >= PSEG) break;
+            const int pix = sg >> 2, sub = sg & 3;
+            const int py = pix / HP, px = pix - py * HP;
+            const int yi = ty0 + py - 1, xi = tx0 + px - 1;
+            rp[q] = (yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi)
+                        ? ld8(src + ((long)yi * a.Wi + xi) * cs + cc + sub * 8)
+                        : zero8();
+        }
+        if (!weights) return;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg >= WSEG) break;
+            const int row = sg >> 2, sub = sg & 3;   // row = tap * BN + n
+            const int tap = row / BN, n = row - tap * BN;
+            rw[q] = n0 + n < a.N ? ld8(a.w + (long)(n0 + n) * a.K + tap * C + c0 + sub * 8) : zero8();
+        }
+    }
+    template <int WLD>
+    __device__ __forceinline__ void store(bf16 (*Ps)[HLD], bf16 (*Ws)[BN][WLD], int tid, bool weights) const {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg >= PSEG) break;
+            *reinterpret_cast<bf16x8*>(&Ps[sg >> 2][(sg & 3) * 8]) = rp[q];
+        }
+        if (!weights) return;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg >= WSEG) break;
+            const int row = sg >> 2;
+            *reinterpret_cast<bf16x8*>(&Ws[row / BN][row % BN][(sg & 3) * 8]) = rw[q];
+        }
+    }
+};
+
+// acc[i][j] += sum over the 9 taps and the staged 32 channels.  With 32 output
+// channels the three kernel rows' weight fragments are held for a fixed kx and
+// each pixel fragment is read once; with 64 the register budget (occupancy 2)
+// allows only the tap-by-tap order.
+template <int BN, int FLIP, int WLD = HLD>
+__device__ __forceinline__ void halo_mma(const bf16 (*Ps)[HLD], const bf16 (*Ws)[BN][WLD], int coff,
+                                         f32x4 (&acc)[4][BN / 16], int lane, int wave) {
+    constexpr int WTN = BN / 16;
+    if constexpr (BN <= 32) {
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            bf16x8 fw[3][WTN];
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+                const int tap = FLIP ? 8 - (3 * ky + kx) : 3 * ky + kx;
+#pragma unroll
+                for (int j = 0; j < WTN; ++j)
+                    fw[ky][j] =
+                        *reinterpret_cast<const bf16x8*>(&Ws[tap][j * 16 + (lane & 15)][coff + (lane >> 4) * 8]);
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const bf16x8 fx =
+                    *reinterpret_cast<const bf16x8*>(&Ps[(wave * 4 + r) * HP + (lane & 15) + kx][(lane >> 4) * 8]);
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) {
+                    const int i = r - ky;          // output row 4w + i reads patch row 4w + i + ky
+                    if (i < 0 || i > 3) continue;
+#pragma unroll
+                    for (int j = 0; j < WTN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[ky][j], fx, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = FLIP ? 2 - tap / 3 : tap / 3, kx = FLIP ? 2 - tap % 3 : tap % 3;
+            bf16x8 fw[WTN];
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                fw[j] = *reinterpret_cast<const bf16x8*>(&Ws[tap][j * 16 + (lane & 15)][coff + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bf16x8 fx = *reinterpret_cast<const bf16x8*>(
+                    &Ps[(wave * 4 + i + ky) * HP + (lane & 15) + kx][(lane >> 4) * 8]);
+#pragma unroll
+                for (int j = 0; j < WTN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fx, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// acc[i][j][e] = D[n = n0 + 16 j + 4 (l/16) + e][pixel (ty0 + 4w + i, tx0 + l%16)]
+template <int BN, int EPI>
+__device__ __forceinline__ void halo_epilogue(const GemmArgs& a, const f32x4 (&acc)[4][BN / 16], int b, int ty0,
+                                              int tx0, int n0, int lane, int wave) {
+    constexpr int WTN = BN / 16;
+    const int x = tx0 + (lane & 15);
+    if (x >= a.Wo) return;
+    const bool vec = (a.N & 3) == 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ty0 + wave * 4 + i;
+        if (y >= a.Ho) continue;
+        const long m = ((long)b * a.Ho + y) * a.Wo + x;
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            const int n = n0 + j * 16 + (lane >> 4) * 4;
+            if (n >= a.N) continue;
+            f32x4 v = acc[i][j];
+            if (EPI == E_FWD) {
+                if (vec) {
+                    const float4 bb = a.bmap ? *reinterpret_cast<const float4*>(a.bmap + ((long)y * a.Wo + x) * a.N + n)
+                                             : *reinterpret_cast<const float4*>(a.bias + n);
+                    v[0] += bb.x;
+                    v[1] += bb.y;
+                    v[2] += bb.z;
+                    v[3] += bb.w;
+                    if (a.resid) {
+                        const bf16x4 r = *reinterpret_cast<const bf16x4*>(a.resid + m * a.N + n);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
+                    }
+                    if (a.relu)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                    if (a.out) {
+                        bf16x4 o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+                        *reinterpret_cast<bf16x4*>(a.out + m * a.N + n) = o;
+                    }
+                    if (a.outf) *reinterpret_cast<f32x4*>(a.outf + m * a.N + n) = v;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (n + e >= a.N) break;
+                        float w = v[e] + (a.bmap ? a.bmap[((long)y * a.Wo + x) * a.N + n + e] : a.bias[n + e]);
+                        if (a.resid) w += (float)a.resid[m * a.N + n + e];
+                        if (a.relu) w = w > 0.f ? w : 0.f;
+                        if (a.out) a.out[m * a.N + n + e] = (bf16)w;
+                        if (a.outf) a.outf[m * a.N + n + e] = w;
+                    }
+                }
+            } else {  // E_ACC
+                const int n2 = a.N - a.n1;
+                if (n + 4 <= a.n1 && (a.n1 & 3) == 0) {
+                    f32x4* p = reinterpret_cast<f32x4*>(a.acc1 + m * a.n1 + n);
+                    *p = *p + v;
+                } else if (n >= a.n1 && n + 4 <= a.N && (n2 & 3) == 0 && ((n - a.n1) & 3) == 0) {
+                    f32x4* p = reinterpret_cast<f32x4*>(a.acc2 + m * n2 + (n - a.n1));
+                    *p = *p + v;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ne = n + e;
+                        if (ne >= a.N) break;
+                        if (ne < a.n1)
+                            a.acc1[m * a.n1 + ne] += v[e];
+                        else
+                            a.acc2[m * n2 + (ne - a.n1)] += v[e];
+                    }
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void halo_count(const GemmArgs& a, unsigned long long* wc, int ty0, int tx0, int n0,
+                                           int bn) {
+    if (!wc) return;
+    const int my = a.Ho - ty0 < HT ? a.Ho - ty0 : HT, mx = a.Wo - tx0 < HT ? a.Wo - tx0 : HT;
+    const int nr = a.N - n0 < bn ? a.N - n0 : bn;
+    atomicAdd(wc, 2ull * my * mx * nr * (unsigned long long)(9 * (a.c1 + a.c2)));
+}
+
+// One tile per block; the next chunk's patch and weights are prefetched into
+// registers while the current chunk runs.
 template <int BN, int FLIP, int EPI>
 __global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long long* wc) {
-    constexpr int WTN = BN / 16;    // MFMA tiles per wave along N
+    constexpr int WTN = BN / 16;
     __shared__ bf16 Ps[HP * HP][HLD];
     __shared__ bf16 Ws[9][BN][HLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -255,118 +522,169 @@ __global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long lo
     const int b = t / tiles_y;
     const int n0 = blockIdx.y * BN;
     if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) return;
-    const int C = a.c1 + a.c2;
-    if (wc && tid == 0) {
-        int my = a.Ho - ty0 < HT ? a.Ho - ty0 : HT, mx = a.Wo - tx0 < HT ? a.Wo - tx0 : HT;
-        int nr = a.N - n0 < BN ? a.N - n0 : BN;
-        atomicAdd(wc, 2ull * my * mx * nr * (unsigned long long)(9 * C));
-    }
+    if (tid == 0) halo_count(a, wc, ty0, tx0, n0, BN);
     f32x4 acc[4][WTN];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < WTN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
-    constexpr int PSEG = HP * HP * (HC / 8);        // 1296 16-byte segments of the patch
-    constexpr int WSEG = 9 * BN * (HC / 8);         // weight segments
-    constexpr int PPT = (PSEG + 255) / 256, WPT = (WSEG + 255) / 256;
-    bf16x8 rp[PPT], rw[WPT];
-    auto load = [&](int c0) {
-        const bool s2 = c0 >= a.c1;
-        const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
-        const int cs = s2 ? a.c2 : a.c1, cc = s2 ? c0 - a.c1 : c0;
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            int sg = tid + q * 256;
-            if (sg >= PSEG) break;
-            int pix = sg >> 2, sub = sg & 3;
-            int py = pix / HP, px = pix - py * HP;
-            int yi = ty0 + py - 1, xi = tx0 + px - 1;
-            rp[q] = (yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi)
-                        ? ld8(src + ((long)yi * a.Wi + xi) * cs + cc + sub * 8)
-                        : zero8();
-        }
-#pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            int sg = tid + q * 256;
-            if (sg >= WSEG) break;
-            int row = sg >> 2, sub = sg & 3;        // row = tap * BN + n
-            int tap = row / BN, n = row - tap * BN;
-            rw[q] = n0 + n < a.N ? ld8(a.w + (long)(n0 + n) * a.K + tap * C + c0 + sub * 8) : zero8();
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            int sg = tid + q * 256;
-            if (sg >= PSEG) break;
-            *reinterpret_cast<bf16x8*>(&Ps[sg >> 2][(sg & 3) * 8]) = rp[q];
-        }
-#pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            int sg = tid + q * 256;
-            if (sg >= WSEG) break;
-            int row = sg >> 2;
-            *reinterpret_cast<bf16x8*>(&Ws[row / BN][row % BN][(sg & 3) * 8]) = rw[q];
-        }
-    };
-    const int nchunk = C / HC;
-    load(0);
+    HaloStage<BN> st;
+    const int nchunk = (a.c1 + a.c2) / HC;
+    st.load(a, tid, b, ty0, tx0, n0, 0, true);
     for (int ch = 0; ch < nchunk; ++ch) {
-        store();
+        st.store(Ps, Ws, tid, true);
         __syncthreads();
-        if (ch + 1 < nchunk) load((ch + 1) * HC);
-        // wave w: tile rows 4w .. 4w+3, each a 16-pixel MFMA row tile
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int ky = FLIP ? 2 - tap / 3 : tap / 3, kx = FLIP ? 2 - tap % 3 : tap % 3;
-            bf16x8 fb[WTN];
-#pragma unroll
-            for (int j = 0; j < WTN; ++j)
-                fb[j] = *reinterpret_cast<const bf16x8*>(&Ws[tap][j * 16 + (lane & 15)][(lane >> 4) * 8]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ty = wave * 4 + i;
-                bf16x8 fa = *reinterpret_cast<const bf16x8*>(&Ps[(ty + ky) * HP + (lane & 15) + kx][(lane >> 4) * 8]);
-#pragma unroll
-                for (int j = 0; j < WTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
-            }
-        }
+        if (ch + 1 < nchunk) st.load(a, tid, b, ty0, tx0, n0, (ch + 1) * HC, true);
+        halo_mma<BN, FLIP>(Ps, Ws, 0, acc, lane, wave);
         __syncthreads();
     }
-    // epilogue: acc[i][j][e] = D[pixel (ty = 4w+i, tx = 4(l/16)+e)][n = j*16 + l%16]
+    halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
+}
+
+// Persistent form for layers of NCH * 32 input channels (NCH = 1, 2) and at most
+// BN output channels: the block loads all its weights into LDS once, walks over
+// (tile, chunk) items with a stride of gridDim.x tiles, and prefetches the next
+// item's patch into registers while the current one runs.
+template <int BN, int FLIP, int EPI, int NCH>
+__global__ __launch_bounds__(256) void k_conv3_pers(GemmArgs a, unsigned long long* wc) {
+    constexpr int WTN = BN / 16;
+    constexpr int WLD = NCH * HC + 8;
+    __shared__ bf16 Ps[HP * HP][HLD];
+    __shared__ bf16 Ws[9][BN][WLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (a.Wo + HT - 1) / HT, tiles_y = (a.Ho + HT - 1) / HT;
+    const int tps = tiles_x * tiles_y;
+    const int ntiles = a.B * tps;
+    const int n0 = blockIdx.y * BN;
+    auto next_tile = [&](int t) {
+        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+            t += gridDim.x;
+        return t;
+    };
+    int t = next_tile(blockIdx.x);
+    if (t >= ntiles) return;   // the same decision for every thread of the block
+    // all weights of the block's output channels, once
+    constexpr int C = NCH * HC;
+    for (int sg = tid; sg < 9 * BN * (C / 8); sg += 256) {
+        const int row = sg / (C / 8), sub = sg - row * (C / 8);   // row = tap * BN + n
+        const int tap = row / BN, n = row - tap * BN;
+        *reinterpret_cast<bf16x8*>(&Ws[tap][n][sub * 8]) =
+            n0 + n < a.N ? ld8(a.w + (long)(n0 + n) * a.K + tap * C + sub * 8) : zero8();
+    }
+    HaloStage<BN> st;
+    st.load(a, tid, t / tps, ((t / tiles_x) % tiles_y) * HT, (t % tiles_x) * HT, n0, 0, false);
+    int ch = 0;
+    f32x4 acc[4][WTN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ty0 + wave * 4 + i;
-        if (y >= a.Ho) continue;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-            const int n = n0 + j * 16 + (lane & 15);
-            if (n >= a.N) continue;
+        for (int j = 0; j < WTN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    while (true) {
+        st.store(Ps, Ws, tid, false);
+        __syncthreads();
+        int tn = t, chn = ch + 1;
+        if (chn == NCH) {
+            chn = 0;
+            tn = next_tile(t + gridDim.x);
+        }
+        if (tn < ntiles)
+            st.load(a, tid, tn / tps, ((tn / tiles_x) % tiles_y) * HT, (tn % tiles_x) * HT, n0, chn * HC, false);
+        halo_mma<BN, FLIP, WLD>(Ps, Ws, ch * HC, acc, lane, wave);
+        __syncthreads();
+        if (ch == NCH - 1) {
+            const int b = t / tps, ty0 = ((t / tiles_x) % tiles_y) * HT, tx0 = (t % tiles_x) * HT;
+            if (tid == 0) halo_count(a, wc, ty0, tx0, n0, BN);
+            halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = tx0 + (lane >> 4) * 4 + e;
-                if (x >= a.Wo) continue;
-                const long m = ((long)b * a.Ho + y) * a.Wo + x;
-                float v = acc[i][j][e];
-                if (EPI == E_FWD) {
-                    v += a.bias[n];
-                    if (a.resid) v += (float)a.resid[m * a.N + n];
-                    if (a.relu) v = v > 0.f ? v : 0.f;
-                    a.out[m * a.N + n] = (bf16)v;
-                    if (a.outf) a.outf[m * a.N + n] = v;
-                } else {
-                    if (n < a.n1)
-                        a.acc1[m * a.n1 + n] += v;
-                    else
-                        a.acc2[m * (a.N - a.n1) + (n - a.n1)] += v;
-                }
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < WTN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+        if (tn >= ntiles) break;
+        t = tn;
+        ch = chn;
+    }
+}
+
+// ------------------------------------------------------------------ first layer (few input channels)
+// 3x3 stride-1 convolution with C <= 4 input channels and N <= 64 outputs (the
+// networks' first layers, C = 2): FP32 FMAs with the weights in LDS.  Thread t
+// of a block computes output channels 8 (t % (N/8)) .. +7 of one pixel, so the
+// lanes of a wave write consecutive 16-byte pieces of the NHWC output.  The
+// implicit GEMM would pad K = 9 C up to 32 and gather element by element.
+constexpr int SC_MAXK = 36, SC_MAXN = 64;
+template <int C>
+__global__ __launch_bounds__(256) void k_conv3_smallc(GemmArgs a, unsigned long long* wc) {
+    __shared__ float Wl[SC_MAXK][SC_MAXN];
+    __shared__ float bl[SC_MAXN];
+    constexpr int K9 = 9 * C;
+    const int N = a.N, G = N / 8;              // 8-channel groups per pixel
+    for (int i = threadIdx.x; i < K9 * N; i += 256) {
+        const int k = i / N, n = i - k * N;
+        Wl[k][n] = (float)a.w[(long)n * a.K + k];
+    }
+    for (int n = threadIdx.x; n < N; n += 256) bl[n] = a.bias[n];
+    __syncthreads();
+    const long nq = a.M * G;
+    if (wc && threadIdx.x == 0) {
+        unsigned long long cnt = 0;
+        for (long q0 = (long)blockIdx.x * 256; q0 < nq; q0 += (long)gridDim.x * 256)
+            cnt += (unsigned long long)(nq - q0 < 256 ? nq - q0 : 256);
+        atomicAdd(wc, 2ull * cnt * 8 * K9);
+    }
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < nq; q += (long)gridDim.x * 256) {
+        const long m = q / G;
+        const int n8 = (int)(q - m * G) * 8;
+        const Pix p = pix_of(m, a.Ho, a.Wo);
+        if (a.st && !(a.st[a.rhs0 + p.b].active && !a.st[a.rhs0 + p.b].cycdone)) continue;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = bl[n8 + e];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int yi = p.y + tap / 3 - 1, xi = p.x + tap % 3 - 1;
+            if (yi < 0 || yi >= a.Hi || xi < 0 || xi >= a.Wi) continue;
+            const bf16* src = a.a1 + p.b * a.abs1 + ((long)yi * a.Wi + xi) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float x = (float)src[c];
+                const float4 w0 = *reinterpret_cast<const float4*>(&Wl[tap * C + c][n8]);
+                const float4 w1 = *reinterpret_cast<const float4*>(&Wl[tap * C + c][n8 + 4]);
+                v[0] += x * w0.x;
+                v[1] += x * w0.y;
+                v[2] += x * w0.z;
+                v[3] += x * w0.w;
+                v[4] += x * w1.x;
+                v[5] += x * w1.y;
+                v[6] += x * w1.z;
+                v[7] += x * w1.w;
             }
+        }
+        if (a.resid) {
+            const bf16x8 r = *reinterpret_cast<const bf16x8*>(a.resid + m * N + n8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] += (float)r[e];
+        }
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
+            o[e] = (bf16)v[e];
+        }
+        *reinterpret_cast<bf16x8*>(a.out + m * N + n8) = o;
+        if (a.outf) {
+            *reinterpret_cast<f32x4*>(a.outf + m * N + n8) = (f32x4){v[0], v[1], v[2], v[3]};
+            *reinterpret_cast<f32x4*>(a.outf + m * N + n8 + 4) = (f32x4){v[4], v[5], v[6], v[7]};
         }
     }
 }
 
-// The halo kernel applies when every source has a multiple of 32 channels.
+static bool smallc_ok(const GemmArgs& a) {
+    return a.gmode == G_CONV && a.stride == 1 && a.epi == E_FWD && !a.bmap && a.c2 == 0 && a.c1 >= 1 && a.c1 <= 4 &&
+           a.N % 8 == 0 && a.N <= SC_MAXN && a.K >= 9 * a.c1;
+}
+
+// The halo kernels apply when every source has a multiple of 32 channels.
 static bool halo_ok(const GemmArgs& a) {
     if (!(a.gmode == G_CONV || a.gmode == G_CONVT) || a.stride != 1) return false;
     if (a.c1 % HC || a.c2 % HC) return false;
@@ -375,22 +693,52 @@ static bool halo_ok(const GemmArgs& a) {
     return a.K >= 9 * (a.c1 + a.c2);
 }
 
+// Resident blocks of a kernel on the whole device (cached per kernel).
+template <typename K>
+static int resident_blocks(K kernel, int& cache) {
+    if (cache > 0) return cache;
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu <= 0)
+        return 256;
+    cache = per_cu * cus;
+    return cache;
+}
+
+template <int BN, int FLIP, int EPI, int NCH>
+static void launch_pers(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
+    static int res = 0;
+    const int ntiles = ((a.Ho + HT - 1) / HT) * ((a.Wo + HT - 1) / HT) * a.B;
+    const int ny = (a.N + BN - 1) / BN;
+    const int slots = resident_blocks(k_conv3_pers<BN, FLIP, EPI, NCH>, res);
+    const int gx = std::max(1, std::min(ntiles, slots / ny));
+    TIMED_LAUNCH("k_conv", s, (k_conv3_pers<BN, FLIP, EPI, NCH>), dim3(gx, ny), dim3(256), 0, s, a, wc);
+}
+
+template <int BN, int FLIP, int EPI>
+static void launch_halo_one(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
+    const int C = a.c1 + a.c2;
+    if (BN == 32 && C == HC) return launch_pers<32, FLIP, EPI, 1>(a, s, wc);
+    if (BN == 32 && C == 2 * HC) return launch_pers<32, FLIP, EPI, 2>(a, s, wc);
+    const int ntiles = ((a.Ho + HT - 1) / HT) * ((a.Wo + HT - 1) / HT) * a.B;
+    TIMED_LAUNCH("k_conv", s, (k_conv3_halo<BN, FLIP, EPI>), dim3(ntiles, (a.N + BN - 1) / BN), dim3(256), 0, s, a,
+                 wc);
+}
+
 static int launch_halo(const GemmArgs& a, hipStream_t s) {
     unsigned long long* wc = WORK_COUNTER("k_conv");
-    const int tiles = ((a.Ho + HT - 1) / HT) * ((a.Wo + HT - 1) / HT) * a.B;
     const bool flip = a.gmode == G_CONVT;
     if (a.N <= 32) {
-        dim3 grid(tiles, (a.N + 31) / 32);
         if (flip)
-            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<32, 1, E_ACC>), grid, dim3(256), 0, s, a, wc);
+            launch_halo_one<32, 1, E_ACC>(a, s, wc);
         else
-            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<32, 0, E_FWD>), grid, dim3(256), 0, s, a, wc);
+            launch_halo_one<32, 0, E_FWD>(a, s, wc);
     } else {
-        dim3 grid(tiles, (a.N + 63) / 64);
         if (flip)
-            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<64, 1, E_ACC>), grid, dim3(256), 0, s, a, wc);
+            launch_halo_one<64, 1, E_ACC>(a, s, wc);
         else
-            TIMED_LAUNCH("k_conv", s, (k_conv3_halo<64, 0, E_FWD>), grid, dim3(256), 0, s, a, wc);
+            launch_halo_one<64, 0, E_FWD>(a, s, wc);
     }
     HELM_CHECK_LAUNCH();
     return HELM_OK;
@@ -414,6 +762,18 @@ int launch_gemm(const GemmArgs& a, hipStream_t s) {
     if (a.K % KC != 0) return fail(HELM_EINVAL, "gemm: K=%d not a multiple of %d", a.K, KC);
     if (a.M <= 0 || a.N <= 0) return HELM_OK;
     if (halo_ok(a)) return launch_halo(a, s);
+    if (smallc_ok(a)) {
+        const dim3 grid((unsigned)std::min<long>(2048, (a.M * (a.N / 8) + 255) / 256));
+        unsigned long long* wc = WORK_COUNTER("k_conv");
+        switch (a.c1) {
+            case 1: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<1>, grid, dim3(256), 0, s, a, wc); break;
+            case 2: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<2>, grid, dim3(256), 0, s, a, wc); break;
+            case 3: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<3>, grid, dim3(256), 0, s, a, wc); break;
+            default: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<4>, grid, dim3(256), 0, s, a, wc); break;
+        }
+        HELM_CHECK_LAUNCH();
+        return HELM_OK;
+    }
     switch (a.gmode) {
         case G_CONV:
             return launch_gemm_mode<G_CONV>(a, s);
