@@ -231,6 +231,20 @@ int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsr
                     int* iters, void* stream);
 
 /*
+ * helm_autotune -- kernel selection for the network's convolutions.  With
+ * autotuning on (the default), the first eager launch of each convolution shape
+ * times every applicable kernel (halo-tiled persistent / one tile per block,
+ * 32 or 64 output channels per block, implicit GEMM with 64x64 or 128x32
+ * tiles, the direct first-layer kernel) on the caller's buffers and keeps the
+ * fastest for that shape for the rest of the process; launches inside a
+ * stream capture use the built-in rule until the shape has been tuned
+ * eagerly.  enable: 1 on, 0 off (built-in rule only), 2 forget the tuned
+ * shapes, -1 leave unchanged.  tuned_shapes (host, may be NULL): number of
+ * shapes tuned so far.
+ */
+int helm_autotune(int enable, int* tuned_shapes);
+
+/*
  * Diagnostics: time every launch of one named kernel ("k_matvec_dot",
  * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",
  * "k_conv_fwd", ...) with HIP events recorded on the stream it is launched on,

@@ -136,6 +136,14 @@ def helm_solve(ops, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float
             np.array(stt[:], dtype=np.int64), code)
 
 
+def helm_autotune(enable: int = -1) -> int:
+    """Convolution kernel autotuning: 1 on, 0 off, 2 forget tuned shapes, -1 query.
+    Returns the number of shapes tuned so far."""
+    n = C.c_int()
+    L.check(L.load().helm_autotune(int(enable), C.byref(n)))
+    return n.value
+
+
 # ---------------------------------------------------------------- encoder-solver network
 class CnnNet:
     """Owning wrapper of a cnn_net_t handle."""

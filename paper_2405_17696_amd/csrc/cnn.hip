@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -64,6 +65,7 @@ struct cnn_net {
     long adam_t = 0;
     bf16* wb = nullptr;        // bf16 forward and data-gradient weight copies
     uint64_t version = 1;      // bumped whenever the parameters change
+    uint64_t uid = 0;          // process-unique id (encoder contexts are keyed by it)
     uint64_t seed = 0;
 };
 
@@ -483,15 +485,29 @@ struct Program {
     float* outf = nullptr;  // fp32 copy of the final output (solver)
 };
 
+// Encoder outputs of one operator for one network version (inference): the
+// context maps z_0..z_3 and the z parts of the solver's context convolutions.
+// Kept per operator, so a batch that alternates between operators of one grid
+// does not re-run the encoder.
+struct EncCtx {
+    uint64_t net_uid = 0, ver = 0;
+    Tens zt[4];              // batch-1 views of z_l
+    float* zc[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<void*> allocs;
+    ~EncCtx() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
 struct Arena {
     int B = 0, H = 0, W = 0;
     bool train = false;
+    const EncCtx* ctx = nullptr;   // inference: context of the operator being applied
     Program enc, sol;
     std::vector<void*> allocs;
     float* work = nullptr;   // wgrad / bias partials
     size_t work_elems = 0;
     float* zg[4] = {nullptr, nullptr, nullptr, nullptr};  // per-sample context gradients
-    float* zc[4] = {nullptr, nullptr, nullptr, nullptr};  // inference: z part (+ bias) of the context convs
     bf16* gm = nullptr;      // masked output gradient (bf16), largest tensor
     ~Arena() {
         for (void* p : allocs) (void)hipFree(p);
@@ -585,12 +601,6 @@ static int alloc_arena(const cnn_net* net, Arena& A) {
         }
     }
     if ((rc = dalloc(A, (void**)&A.sol.outf, sizeof(float) * A.sol.t[A.sol.output].n()))) return rc;
-    if (!A.train) {
-        for (int l = 0; l < 4; ++l) {
-            const Tens& z = A.enc.t[A.enc.z[l]];
-            if ((rc = dalloc(A, (void**)&A.zc[l], sizeof(float) * (long)z.H * z.W * z.C))) return rc;
-        }
-    }
     if (A.train) {
         for (int l = 0; l < 4; ++l) {
             const Tens& z = A.enc.t[A.enc.z[l]];
@@ -615,7 +625,8 @@ static int alloc_arena(const cnn_net* net, Arena& A) {
 
 // ------------------------------------------------------------------ forward / backward
 static const Tens& tens_of(const Arena& A, const Program& P, int id) {
-    return id <= -2 ? A.enc.t[A.enc.z[-id - 2]] : P.t[id];
+    if (id <= -2) return A.ctx ? A.ctx->zt[-id - 2] : A.enc.t[A.enc.z[-id - 2]];
+    return P.t[id];
 }
 
 static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState* st, int rhs0, hipStream_t s) {
@@ -638,7 +649,7 @@ static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState*
         g.out = y.d;
         g.st = (&P == &A.sol) ? st : nullptr;
         g.rhs0 = rhs0;
-        const bool split = L.ctx && !A.train && op.bcast2 && op.in2 <= -2;
+        const bool split = L.ctx && A.ctx && op.bcast2 && op.in2 <= -2;
         if (op.in2 != -1 && !split) {
             const Tens& x2 = tens_of(A, P, op.in2);
             g.a2 = x2.d;
@@ -649,7 +660,7 @@ static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState*
             // conv(concat(h, z)) = conv_h(h) + [conv_z(z) + b], the bracket precomputed per encoder pass
             g.w = net->wb + L.wh_off;
             g.K = L.Kh;
-            g.bmap = A.zc[-op.in2 - 2];
+            g.bmap = A.ctx->zc[-op.in2 - 2];
         }
         if (op.kind == OP_CONV) {
             g.gmode = G_CONV;
@@ -857,20 +868,25 @@ static int check_grid(const helm_op* op) {
 }
 
 // Encoder pass for (net, op) into the arena's encoder program.
-static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s) {
+static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s, EncCtx* ctx = nullptr) {
     long n = op->n();
     float sc = (float)(op->omega * op->omega * op->hx * op->hz);
     hipLaunchKernelGGL(k_enc_input, g1(n), dim3(256), 0, s, op->lv[0].k2, op->lv[0].g, n, sc,
                        A.enc.t[A.enc.input].d);
     HELM_CHECK_LAUNCH();
+    A.ctx = nullptr;
     int rc = run_forward(net, A, A.enc, nullptr, 0, s);
-    if (rc || A.train) return rc;
+    if (rc || !ctx) return rc;
+    for (int l = 0; l < 4; ++l) {
+        const Tens& z = A.enc.t[A.enc.z[l]];
+        HELM_HIP(hipMemcpyAsync(ctx->zt[l].d, z.d, sizeof(bf16) * z.n(), hipMemcpyDeviceToDevice, s));
+    }
     // z parts of the solver's context convolutions (batch independent)
     for (const Op& o : A.sol.ops) {
         const LayerDesc& L = net->layers[o.layer];
         if (!L.ctx || o.in2 > -2) continue;
         const int l = -o.in2 - 2;
-        const Tens& z = A.enc.t[A.enc.z[l]];
+        const Tens& z = ctx->zt[l];
         GemmArgs g{};
         g.gmode = G_CONV;
         g.a1 = z.d;
@@ -890,19 +906,12 @@ static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s) {
         g.bias = net->master + L.boff;
         g.relu = 0;
         g.out = nullptr;
-        g.outf = A.zc[l];
+        g.outf = ctx->zc[l];
         g.M = (long)z.H * z.W;
         if ((rc = launch_gemm(g, s))) return rc;
     }
     return HELM_OK;
 }
-
-// Inference arenas keep the encoder context of the last (op, version) pair.
-struct EncKey {
-    const helm_op* op;
-    uint64_t ver;
-};
-static std::map<Arena*, EncKey> g_enc_key;
 
 int cnn_prepare(cnn_net* net, const helm_op* op, hipStream_t s) {
     (void)net;
@@ -911,18 +920,48 @@ int cnn_prepare(cnn_net* net, const helm_op* op, hipStream_t s) {
     return HELM_OK;
 }
 
+// Makes A->ctx the encoder context of (net, op), running the encoder only when
+// the operator has none for this network version.
 static int ensure_encoded(cnn_net* net, const helm_op* op, Arena* A, hipStream_t s) {
-    auto it = g_enc_key.find(A);
-    if (it != g_enc_key.end() && it->second.op == op && it->second.ver == net->version) return HELM_OK;
-    int rc = encode(net, op, *A, s);
+    EncCtx* ctx = (EncCtx*)op->enc.ctx;
+    if (ctx && ctx->net_uid == net->uid && ctx->ver == net->version) {
+        A->ctx = ctx;
+        return HELM_OK;
+    }
+    if (!ctx) {
+        ctx = new EncCtx();
+        for (int l = 0; l < 4; ++l) {
+            Tens t = A->enc.t[A->enc.z[l]];
+            t.g = nullptr;
+            void* p = nullptr;
+            if (hipMalloc(&p, sizeof(bf16) * t.n()) != hipSuccess) {
+                delete ctx;
+                return fail(HELM_ENOMEM, "cnn: encoder context");
+            }
+            ctx->allocs.push_back(p);
+            t.d = (bf16*)p;
+            ctx->zt[l] = t;
+            if (hipMalloc(&p, sizeof(float) * t.n()) != hipSuccess) {
+                delete ctx;
+                return fail(HELM_ENOMEM, "cnn: encoder context");
+            }
+            ctx->allocs.push_back(p);
+            ctx->zc[l] = (float*)p;
+        }
+        const_cast<helm_op*>(op)->enc.ctx = ctx;
+    }
+    ctx->net_uid = 0;
+    int rc = encode(net, op, *A, s, ctx);
     if (rc) return rc;
-    g_enc_key[A] = {op, net->version};
+    ctx->net_uid = net->uid;
+    ctx->ver = net->version;
+    A->ctx = ctx;
     return HELM_OK;
 }
 
 void cnn_release_cache(helm_op* op) {
-    for (auto& kv : g_enc_key)
-        if (kv.second.op == op) kv.second.op = nullptr;
+    delete (EncCtx*)op->enc.ctx;
+    op->enc.ctx = nullptr;
 }
 
 // e = M_net(r) for nrhs vectors.  Scales: s_in = sqrt(N) fscale (FGMRES basis
@@ -1152,6 +1191,8 @@ int cnn_create(const cnn_arch* arch, uint64_t seed, cnn_net_t* out) {
     if (!out) return fail(HELM_EINVAL, "cnn_create: out is NULL");
     *out = nullptr;
     cnn_net* n = new cnn_net();
+    static std::atomic<uint64_t> next_uid{1};
+    n->uid = next_uid++;
     if (arch) {
         for (int l = 0; l < 4; ++l)
             if (arch->widths[l] > 0) n->widths[l] = arch->widths[l];
@@ -1219,10 +1260,7 @@ void cnn_destroy(cnn_net_t n) {
     (void)hipDeviceSynchronize();
     auto it = g_state.find(n);
     if (it != g_state.end()) {
-        for (auto& kv : it->second.arenas) {
-            g_enc_key.erase(kv.second);
-            delete kv.second;
-        }
+        for (auto& kv : it->second.arenas) delete kv.second;
         g_state.erase(it);
     }
     if (n->master) (void)hipFree(n->master);
@@ -1636,3 +1674,8 @@ int cnn_precond_train(cnn_net_t n, helm_op_t op, const cnn_train_opts* opt, uint
 }
 
 }  // extern "C"
+
+extern "C" int helm_autotune(int enable, int* tuned_shapes) {
+    if (enable < -1 || enable > 2) return fail(HELM_EINVAL, "helm_autotune: enable must be -1, 0, 1 or 2");
+    return conv_autotune(enable, tuned_shapes);
+}

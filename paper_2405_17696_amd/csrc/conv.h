@@ -71,6 +71,8 @@ struct WgradArgs {
 };
 
 int launch_gemm(const GemmArgs& a, hipStream_t s);
+// enable: 1 on, 0 off (built-in rule), 2 forget the tuned shapes; -1 query only.
+int conv_autotune(int enable, int* tuned);
 int launch_wgrad(const WgradArgs& a, int nsplit, hipStream_t s);
 
 }  // namespace helm

@@ -10,6 +10,8 @@
 // passes the weights as A and the pixels as B, so that the accumulators of a
 // lane are four consecutive output channels of one pixel (vector stores).
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "conv.h"
 
@@ -717,75 +719,204 @@ static void launch_pers(const GemmArgs& a, hipStream_t s, unsigned long long* wc
 }
 
 template <int BN, int FLIP, int EPI>
-static void launch_halo_one(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
-    const int C = a.c1 + a.c2;
-    if (BN == 32 && C == HC) return launch_pers<32, FLIP, EPI, 1>(a, s, wc);
-    if (BN == 32 && C == 2 * HC) return launch_pers<32, FLIP, EPI, 2>(a, s, wc);
+static void launch_single(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
     const int ntiles = ((a.Ho + HT - 1) / HT) * ((a.Wo + HT - 1) / HT) * a.B;
     TIMED_LAUNCH("k_conv", s, (k_conv3_halo<BN, FLIP, EPI>), dim3(ntiles, (a.N + BN - 1) / BN), dim3(256), 0, s, a,
                  wc);
 }
 
-static int launch_halo(const GemmArgs& a, hipStream_t s) {
-    unsigned long long* wc = WORK_COUNTER("k_conv");
-    const bool flip = a.gmode == G_CONVT;
-    if (a.N <= 32) {
-        if (flip)
-            launch_halo_one<32, 1, E_ACC>(a, s, wc);
+template <int GM, int BM, int BN, int WGM, int WGN>
+static void launch_gemm_tile(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
+    dim3 grid((unsigned)((a.M + BM - 1) / BM), (a.N + BN - 1) / BN);
+    TIMED_LAUNCH("k_conv", s, (k_gemm<GM, BM, BN, WGM, WGN>), grid, dim3(256), 0, s, a, wc);
+}
+
+template <int GM>
+static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long long* wc, bool tall) {
+    if (tall)
+        launch_gemm_tile<GM, 128, 32, 4, 1>(a, s, wc);
+    else
+        launch_gemm_tile<GM, 64, 64, 2, 2>(a, s, wc);
+}
+
+// ------------------------------------------------------------------ kernel choice and autotuning
+// Every convolution launch picks one of these kernels.  A built-in rule gives
+// the default; with autotuning on, the first eager launch of each problem shape
+// (outside stream capture) times every applicable candidate on the caller's
+// buffers and keeps the fastest for that shape.  Only overwriting epilogues are
+// tuned (accumulating ones would add each candidate's result).
+enum ConvKernel { CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_COUNT };
+
+static bool ck_applicable(const GemmArgs& a, int ck) {
+    const bool halo = halo_ok(a);
+    const int C = a.c1 + a.c2;
+    switch (ck) {
+        case CK_PERS: return halo && a.N <= 32 && (C == HC || C == 2 * HC);
+        case CK_HALO32: return halo;
+        case CK_HALO64: return halo;
+        case CK_GEMM64:
+        case CK_GEMM128: return true;
+        case CK_SMALLC: return smallc_ok(a);
+    }
+    return false;
+}
+
+static int ck_default(const GemmArgs& a) {
+    if (halo_ok(a)) {
+        if (ck_applicable(a, CK_PERS)) return CK_PERS;
+        return a.N <= 32 ? CK_HALO32 : CK_HALO64;
+    }
+    if (smallc_ok(a)) return CK_SMALLC;
+    return a.N <= 32 ? CK_GEMM128 : CK_GEMM64;
+}
+
+template <int FLIP, int EPI>
+static void launch_halo_ck(const GemmArgs& a, hipStream_t s, unsigned long long* wc, int ck) {
+    const int C = a.c1 + a.c2;
+    if (ck == CK_PERS) {
+        if (C == HC)
+            launch_pers<32, FLIP, EPI, 1>(a, s, wc);
         else
-            launch_halo_one<32, 0, E_FWD>(a, s, wc);
+            launch_pers<32, FLIP, EPI, 2>(a, s, wc);
+    } else if (ck == CK_HALO32) {
+        launch_single<32, FLIP, EPI>(a, s, wc);
     } else {
-        if (flip)
-            launch_halo_one<64, 1, E_ACC>(a, s, wc);
-        else
-            launch_halo_one<64, 0, E_FWD>(a, s, wc);
+        launch_single<64, FLIP, EPI>(a, s, wc);
+    }
+}
+
+static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long long* wc) {
+    switch (ck) {
+        case CK_PERS:
+        case CK_HALO32:
+        case CK_HALO64:
+            if (a.gmode == G_CONVT)
+                launch_halo_ck<1, E_ACC>(a, s, wc, ck);
+            else
+                launch_halo_ck<0, E_FWD>(a, s, wc, ck);
+            break;
+        case CK_SMALLC: {
+            const dim3 grid((unsigned)std::min<long>(2048, (a.M * (a.N / 8) + 255) / 256));
+            switch (a.c1) {
+                case 1: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<1>, grid, dim3(256), 0, s, a, wc); break;
+                case 2: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<2>, grid, dim3(256), 0, s, a, wc); break;
+                case 3: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<3>, grid, dim3(256), 0, s, a, wc); break;
+                default: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<4>, grid, dim3(256), 0, s, a, wc); break;
+            }
+            break;
+        }
+        default: {
+            const bool tall = ck == CK_GEMM128;
+            switch (a.gmode) {
+                case G_CONV: launch_gemm_pick<G_CONV>(a, s, wc, tall); break;
+                case G_CONVT: launch_gemm_pick<G_CONVT>(a, s, wc, tall); break;
+                case G_UP: launch_gemm_pick<G_UP>(a, s, wc, tall); break;
+                case G_UPT: launch_gemm_pick<G_UPT>(a, s, wc, tall); break;
+                default: return fail(HELM_EINVAL, "gemm: gather mode %d", a.gmode);
+            }
+        }
     }
     HELM_CHECK_LAUNCH();
     return HELM_OK;
 }
 
-template <int GM>
-static int launch_gemm_mode(const GemmArgs& a, hipStream_t s) {
-    unsigned long long* wc = WORK_COUNTER("k_conv");
-    if (a.N <= 32) {
-        dim3 grid((unsigned)((a.M + 127) / 128), (a.N + 31) / 32);
-        TIMED_LAUNCH("k_conv", s, (k_gemm<GM, 128, 32, 4, 1>), grid, dim3(256), 0, s, a, wc);
-    } else {
-        dim3 grid((unsigned)((a.M + 63) / 64), (a.N + 63) / 64);
-        TIMED_LAUNCH("k_conv", s, (k_gemm<GM, 64, 64, 2, 2>), grid, dim3(256), 0, s, a, wc);
+namespace {
+struct TuneKey {
+    int v[16];
+    bool operator<(const TuneKey& o) const {
+        for (int i = 0; i < 16; ++i)
+            if (v[i] != o.v[i]) return v[i] < o.v[i];
+        return false;
     }
-    HELM_CHECK_LAUNCH();
+};
+std::map<TuneKey, int> g_tuned;
+std::mutex g_tune_mutex;
+bool g_tune_on = true;
+
+TuneKey tune_key(const GemmArgs& a) {
+    TuneKey k{};
+    int i = 0;
+    k.v[i++] = a.gmode;
+    k.v[i++] = a.epi;
+    k.v[i++] = a.stride;
+    k.v[i++] = a.c1;
+    k.v[i++] = a.c2;
+    k.v[i++] = a.abs2 == 0;
+    k.v[i++] = a.N;
+    k.v[i++] = a.K;
+    k.v[i++] = a.B;
+    k.v[i++] = a.Hi;
+    k.v[i++] = a.Wi;
+    k.v[i++] = a.Ho;
+    k.v[i++] = a.Wo;
+    k.v[i++] = (a.resid != nullptr) | (a.outf != nullptr) << 1 | (a.bmap != nullptr) << 2 | (a.relu != 0) << 3;
+    k.v[i++] = a.st != nullptr;
+    return k;
+}
+
+bool capturing_stream(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Times every applicable candidate (1 warm-up + 3 timed launches each).
+int tune(const GemmArgs& a, hipStream_t s, int* best) {
+    hipEvent_t e0, e1;
+    HELM_HIP(hipEventCreate(&e0));
+    HELM_HIP(hipEventCreate(&e1));
+    float best_ms = 0;
+    *best = ck_default(a);
+    for (int ck = 0; ck < CK_COUNT; ++ck) {
+        if (!ck_applicable(a, ck)) continue;
+        int rc = launch_ck(a, s, ck, nullptr);
+        if (rc) return rc;
+        HELM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r)
+            if ((rc = launch_ck(a, s, ck, nullptr))) return rc;
+        HELM_HIP(hipEventRecord(e1, s));
+        HELM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ck == ck_default(a)) ms *= 0.97f;    // keep the rule's choice within noise
+        if (best_ms == 0 || ms < best_ms) {
+            best_ms = ms;
+            *best = ck;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return HELM_OK;
 }
+}  // namespace
 
 int launch_gemm(const GemmArgs& a, hipStream_t s) {
     if (a.K % KC != 0) return fail(HELM_EINVAL, "gemm: K=%d not a multiple of %d", a.K, KC);
     if (a.M <= 0 || a.N <= 0) return HELM_OK;
-    if (halo_ok(a)) return launch_halo(a, s);
-    if (smallc_ok(a)) {
-        const dim3 grid((unsigned)std::min<long>(2048, (a.M * (a.N / 8) + 255) / 256));
-        unsigned long long* wc = WORK_COUNTER("k_conv");
-        switch (a.c1) {
-            case 1: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<1>, grid, dim3(256), 0, s, a, wc); break;
-            case 2: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<2>, grid, dim3(256), 0, s, a, wc); break;
-            case 3: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<3>, grid, dim3(256), 0, s, a, wc); break;
-            default: TIMED_LAUNCH("k_conv", s, k_conv3_smallc<4>, grid, dim3(256), 0, s, a, wc); break;
+    int ck = ck_default(a);
+    const bool tunable = (a.epi == E_FWD || a.epi == E_UPFWD) && a.out != nullptr;
+    if (tunable) {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        if (g_tune_on) {
+            const TuneKey key = tune_key(a);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) {
+                ck = it->second;
+            } else if (!capturing_stream(s)) {
+                int rc = tune(a, s, &ck);
+                if (rc) return rc;
+                g_tuned[key] = ck;
+            }
         }
-        HELM_CHECK_LAUNCH();
-        return HELM_OK;
     }
-    switch (a.gmode) {
-        case G_CONV:
-            return launch_gemm_mode<G_CONV>(a, s);
-        case G_CONVT:
-            return launch_gemm_mode<G_CONVT>(a, s);
-        case G_UP:
-            return launch_gemm_mode<G_UP>(a, s);
-        case G_UPT:
-            return launch_gemm_mode<G_UPT>(a, s);
-        default:
-            return fail(HELM_EINVAL, "gemm: gather mode %d", a.gmode);
-    }
+    return launch_ck(a, s, ck, WORK_COUNTER("k_conv"));
+}
+
+int conv_autotune(int enable, int* tuned) {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    if (enable == 0 || enable == 1) g_tune_on = enable == 1;
+    if (enable == 2) g_tuned.clear();
+    if (tuned) *tuned = (int)g_tuned.size();
+    return HELM_OK;
 }
 
 // ------------------------------------------------------------------ weight gradient

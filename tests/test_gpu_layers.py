@@ -88,3 +88,20 @@ def test_upconv_layer_forward_backward(gpu, B, H, W_, cin, cout):
     assert relerr(gx, rx) <= 1e-5
     assert relerr(gw, rw) <= 1e-5
     assert relerr(gb, rb) <= 1e-5
+
+
+def test_autotuner_choice_keeps_results(gpu):
+    """Tuned and rule-based kernel choices give the same layer within BF16 rounding."""
+    x1 = rnd((2, 40, 48, 32), 11)
+    Wt = rnd((32, 3, 3, 32), 12, scale=np.sqrt(2.0 / 288))
+    b = rnd((32,), 13, 0.1)
+    ref = np.maximum(U.conv3x3(x1, Wt, b, 1), 0)
+    api.helm_autotune(2)
+    api.helm_autotune(0)
+    y0 = api.cnn_layer_forward(0, 1, x1, Wt, b, relu=True)
+    n0 = api.helm_autotune(-1)
+    api.helm_autotune(1)
+    y1 = api.cnn_layer_forward(0, 1, x1, Wt, b, relu=True)
+    n1 = api.helm_autotune(-1)
+    assert n0 == 0 and n1 >= 1
+    assert relerr(y0, ref) <= 1e-5 and relerr(y1, ref) <= 1e-5
