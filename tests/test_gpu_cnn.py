@@ -61,13 +61,15 @@ def test_forward_parity(gpu, nz, nx):
     assert relerr(out, ref) <= 3e-2
 
 
-def test_forward_parity_full_width(gpu):
-    """Default architecture (32-256, two residual blocks per encoder level)."""
+@pytest.mark.parametrize("nz,nx,B", [(32, 32, 1), (48, 80, 3)])
+def test_forward_parity_full_width(gpu, nz, nx, B):
+    """Default architecture (32-256, two residual blocks per encoder level); the
+    48 x 80 case spans several 16 x 16 tiles with ragged edges on every level."""
     widths = (32, 64, 128, 256)
-    med = medium(32, 32, seed=9)
+    med = medium(nz, nx, seed=9)
     H = setup(med)
     net, theta = small_net(seed=11, widths=widths, down_res=2)
-    rin = np.random.default_rng(6).standard_normal((1, 32, 32, 2)).astype(np.float32)
+    rin = np.random.default_rng(6).standard_normal((B, nz, nx, 2)).astype(np.float32)
     out = api.cnn_forward(net, H, torch.tensor(rin, device="cuda")).cpu().numpy()
     enc = U.encoder_input(med.kappa2, med.gamma, med.omega, med.h, med.h)
     ref, _ = U.network_forward(theta, enc, rin.astype(np.float64), widths, 2)
