@@ -1,24 +1,35 @@
 #!/usr/bin/env python3
 """Helmholtz right-hand sides solved per second at relative residual 1e-6, one MI355X.
 
-Workload: 256x256 layered medium (8 random layers, 1.5-4.5 km/s, x(1+0.1 GRF)),
-16-cell absorbing layer, 10 points per minimum wavelength, 32 surface point
-sources, all solved in one batched flexible-GMRES call.  One step = operator
-setup (coefficients + multigrid hierarchy + coarse polynomial) + encoder pass
-(CNN preconditioner) + the batched solve of all 32 right-hand sides to an FP64
-relative residual of 1e-6.  Inputs are resident in HBM before timing starts.
+Default workload (the headline): 256x256 layered medium (8 random layers,
+1.5-4.5 km/s, x(1+0.1 GRF)), 16-cell absorbing layer, 10 points per minimum
+wavelength, 32 surface point sources, all solved in one batched flexible-GMRES
+call.  One step = operator setup (coefficients + multigrid hierarchy + coarse
+polynomial) + encoder pass (CNN preconditioner) + the batched solve of all 32
+right-hand sides to an FP64 relative residual of 1e-6.  Inputs are resident in
+HBM before timing starts.
 
-Prints one JSON line.  `value` is the CNN-FGMRES rate (M_VU: network + V-cycle,
-FGMRES(20)); the MG-GMRES(20) rate on the same right-hand sides and GPU is in
+Prints one JSON line.  `value` is the CNN-FGMRES(10) rate (M_VU: network +
+V-cycle); the MG-GMRES(20) rate on the same right-hand sides and GPU is in
 `compare`.  The network is trained before the timed region by the library's
 own kernels on pairs generated on the workload medium (eq. 4.3), the
 retraining regime of the paper in which the network is adapted to the current
 model; its training throughput is reported in `training`.
+
+Other workloads (--workload), each one JSON line of measurements:
+  c3  uneven batch: 3 grids x 3 frequencies x 64 sources (576 systems) in one
+      masked MG-GMRES(20) launch, eager and graph-replayed;
+  c4  retraining: network trained on the c2 medium, then retrained (200 Adam
+      steps, lr 1e-4, 2000 pairs) on the 5%-perturbed medium; FGMRES iteration
+      counts before / after / MG;
+  c5  FWI misfit gradient: 512x512, 128 sources, 128 receivers, 4 frequencies,
+      forward + adjoint solves through fwi_misfit_grad.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -39,10 +50,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--precond", default="cnn_vu", choices=["mg", "cnn_vu", "cnn"])
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-lr", type=float, default=1e-3)
-    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--restart", type=int, default=10, help="FGMRES cycle length of the CNN preconditioners")
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rhs", type=int, default=1)
@@ -51,11 +63,12 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the graph-replay and MG comparison runs")
     ap.add_argument("--kernel", default=None, help="kernel whose roofline is reported")
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
-    ap.add_argument("--no-graph", action="store_true", help="launch each restart cycle eagerly")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
+    ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
     return ap.parse_args()
 
 
-def kernel_roofline(api_lib, name, unit_bytes=True):
+def kernel_roofline(api_lib, name):
     import ctypes as C
     n = C.c_int()
     ms = C.c_double()
@@ -99,11 +112,42 @@ def cpu_baseline(med, src, nrhs):
                       f"{dt:.1f} s, iterations {its}"}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-        sys.exit(2)
+def train_on(api, net, k2, gam, med, steps, lr0, seed0=100):
+    """Rounds of 500 Adam steps on fresh eq. (4.3) pairs; lr / 3 after two rounds."""
+    import torch
+    op_t = api.helm_setup(k2, gam, med.omega, med.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    left, rnd, hist, lr = steps, 0, [], lr0
+    while left > 0:
+        chunk = min(500, left)
+        h, _ = api.cnn_precond_train(net, op_t, npairs=2048, batch=16, steps=chunk, lr=lr, seed=seed0 + rnd)
+        hist += list(h)
+        left -= chunk
+        rnd += 1
+        if rnd == 2:
+            lr /= 3
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    op_t.close()
+    return {"steps": steps, "batch": 16, "pairs_per_round": 2048, "seconds": tt,
+            "ms_per_step_incl_data": 1e3 * tt / max(1, steps),
+            "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:]))}
+
+
+def get_net(api, a, k2, gam, med):
+    training = None
+    if a.net:
+        net = api.cnn_load(a.net)
+    else:
+        net = api.cnn_create(seed=1)
+        training = train_on(api, net, k2, gam, med, a.train_steps, a.train_lr)
+    if a.save_net:
+        api.cnn_save(net, a.save_net)
+    return net, training
+
+
+def main_c2(a):
     import torch
     from paper_2405_17696_amd import _lib, api, synth
     lib = _lib.load()
@@ -115,54 +159,29 @@ def main():
     b = torch.tensor(src, dtype=torch.complex64, device=dev)
     x = torch.empty(b.shape, dtype=torch.complex128, device=dev)
 
-    net = None
+    net, training = None, None
     precond = a.precond
     kernel = a.kernel or DOMINANT[precond]
-    training = None
     if precond != "mg":
-        if a.net:
-            net = api.cnn_load(a.net)
-        else:
-            net = api.cnn_create(seed=1)
-            op_t = api.helm_setup(k2, gam, med.omega, med.h)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            steps_left, rnd, hist = a.train_steps, 0, []
-            lr = a.train_lr
-            while steps_left > 0:
-                chunk = min(500, steps_left)
-                h, _ = api.cnn_precond_train(net, op_t, npairs=2048, batch=16, steps=chunk, lr=lr, seed=100 + rnd)
-                hist += list(h)
-                steps_left -= chunk
-                rnd += 1
-                if rnd == 2:
-                    lr /= 3
-            torch.cuda.synchronize()
-            tt = time.perf_counter() - t0
-            training = {"steps": a.train_steps, "batch": 16, "pairs_per_round": 2048, "seconds": tt,
-                        "ms_per_step_incl_data": 1e3 * tt / max(1, a.train_steps),
-                        "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:]))}
-            op_t.close()
-        if a.save_net:
-            api.cnn_save(net, a.save_net)
+        net, training = get_net(api, a, k2, gam, med)
 
-    def step(pc):
+    def step(pc, restart, use_graph):
         op = api.helm_setup(k2, gam, med.omega, med.h)
         out = api.helm_solve(op, b, x, tol=1e-6, precond=pc, maxit=a.maxit, net=net, reorth=a.reorth,
-                             use_graph=not a.no_graph, restart=a.restart)
+                             use_graph=use_graph, restart=restart)
         op.close()
         return out
 
-    def run(pc, steps, warmup, timer=None):
+    def run(pc, steps, warmup, restart, use_graph=False, timer=None):
         for _ in range(warmup):
-            step(pc)
+            step(pc, restart, use_graph)
         torch.cuda.synchronize()
         if timer:
             _lib.check(lib.helm_ktimer_start(timer.encode()))
         t0 = time.perf_counter()
         last = None
         for _ in range(steps):
-            last = step(pc)
+            last = step(pc, restart, use_graph)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         roof = kernel_roofline(lib, timer) if timer else None
@@ -170,27 +189,28 @@ def main():
             _lib.check(lib.helm_ktimer_start(None))
         return dt, last, roof
 
+    restart = a.restart if precond != "mg" else 20
     # timed region: eager launches with the dominant kernel bracketed by events
     # (kernels inside a replayed graph cannot carry per-launch events); the
     # graph-replay rate of the same step is reported beside it
-    graph_mode = not a.no_graph
-    a.no_graph = True
-    dt, last, roof = run(precond, a.steps, a.warmup, timer=kernel)
-    a.no_graph = not graph_mode
-    graph_rate = None
-    if graph_mode and not a.no_compare:
-        dtg, lastg, _ = run(precond, a.steps, 1)
-        graph_rate = nrhs * a.steps / dtg
+    dt, last, roof = run(precond, a.steps, a.warmup, restart, timer=kernel)
     _, it, rr, st, code = last
     if code != 0:
         raise SystemExit(f"solve did not converge: status {st.tolist()} relres {rr.tolist()}")
     value = nrhs * a.steps / dt
-    compare = {precond: {"rhs_per_s": value, "iters_mean": float(it.mean()), "iters_max": int(it.max()),
-                         "relres_max": float(rr.max()), "rhs_per_s_graph_replay": graph_rate}}
-    if precond != "mg" and not a.no_compare:
-        dtm, lastm, _ = run("mg", max(1, a.steps // 2), 1)
-        compare["mg"] = {"rhs_per_s": nrhs * max(1, a.steps // 2) / dtm, "iters_mean": float(lastm[1].mean())}
-        compare["speedup_vs_mg"] = value / compare["mg"]["rhs_per_s"]
+    compare = {precond: {"rhs_per_s": value, "restart": restart, "iters_mean": float(it.mean()),
+                         "iters_max": int(it.max()), "relres_max": float(rr.max())}}
+    if not a.no_compare:
+        if not a.no_graph:
+            dtg, _, _ = run(precond, a.steps, 1, restart, use_graph=True)
+            compare[precond]["rhs_per_s_graph_replay"] = nrhs * a.steps / dtg
+        if precond != "mg":
+            k = max(1, a.steps // 2)
+            dt20, last20, _ = run(precond, k, 1, 20)
+            compare[precond + "_restart20"] = {"rhs_per_s": nrhs * k / dt20, "iters_mean": float(last20[1].mean())}
+            dtm, lastm, _ = run("mg", k, 1, 20)
+            compare["mg"] = {"rhs_per_s": nrhs * k / dtm, "restart": 20, "iters_mean": float(lastm[1].mean())}
+            compare["speedup_vs_mg"] = value / compare["mg"]["rhs_per_s"]
 
     roofline = None
     if roof and kernel == "k_conv":
@@ -212,10 +232,135 @@ def main():
            "dtype": ("bf16 network / " if precond != "mg" else "") + "c64 Krylov / c128 iterate / f64 residual",
            "data": "synthetic",
            "config": {"workload": "256x256 layered+GRF medium, 10 ppw, 32 surface sources, tol 1e-6",
-                      "precond": precond, "restart": a.restart, "global_batch": nrhs, "grid": [256, 256],
+                      "precond": precond, "restart": restart, "global_batch": nrhs, "grid": [256, 256],
                       "parallelism": "single GPU"},
-           "compare": compare, "roofline": roofline, "cpu_baseline": cpu, "training": training}
+           "compare": compare, "roofline": roofline, "cpu_baseline": cpu, "training": training,
+           "autotuned_shapes": api.helm_autotune(-1)}
     print(json.dumps(out))
+
+
+def main_c3(a):
+    import torch
+    from paper_2405_17696_amd import api, synth
+    nsrc = a.sources or 64
+    items = synth.config3_media(nsrc=nsrc)
+    ops, rhs_op, parts = [], [], []
+    for k, (med, src) in enumerate(items):
+        k2 = torch.tensor(med.kappa2, dtype=torch.float32, device="cuda")
+        g = torch.tensor(med.gamma, dtype=torch.float32, device="cuda")
+        ops.append(api.helm_setup(k2, g, med.omega, med.h))
+        parts.append(src.reshape(-1))
+        rhs_op += [k] * src.shape[0]
+    b = torch.tensor(np.concatenate(parts), dtype=torch.complex64, device="cuda")
+    res = {}
+    for use_graph in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, rr, st, code = api.helm_solve(ops, b, tol=1e-6, rhs_op=rhs_op, precond="mg", maxit=a.maxit,
+                                             restart=20, use_graph=use_graph)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        conv = int((st == 0).sum())
+        groups = []
+        for k, (med, _) in enumerate(items):
+            sel = [i for i, o in enumerate(rhs_op) if o == k]
+            ppw = 2 * math.pi * med.c_min / (med.omega * med.h)
+            groups.append({"grid": list(med.kappa2.shape), "ppw": round(ppw, 2),
+                           "iters_mean": float(it[sel].mean()), "iters_max": int(it[sel].max()),
+                           "converged": int((st[sel] == 0).sum()), "systems": len(sel)})
+        res["graph" if use_graph else "eager"] = {"seconds": dt, "converged": conv, "systems": len(rhs_op),
+                                                 "converged_rhs_per_s": conv / dt, "groups": groups}
+        print(f"c3 {'graph' if use_graph else 'eager'} done in {dt:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "c3 uneven batch: 256x512, 384x768, 512x1024 x 5/8/12 ppw x "
+                                  f"{nsrc} sources, MG-GMRES(20), tol 1e-6, maxit {a.maxit}",
+                      "systems": len(rhs_op), "node_rhs": int(b.numel()), "results": res}))
+
+
+def main_c4(a):
+    import torch
+    from paper_2405_17696_amd import api, synth
+    med2, src = synth.config2_medium()
+    med4 = synth.config4_medium()
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    b = torch.tensor(src, dtype=torch.complex64, device="cuda")
+    net, training = get_net(api, a, t(med2.kappa2), t(med2.gamma), med2)
+
+    def iters(pc, m):
+        op = api.helm_setup(t(m.kappa2), t(m.gamma), m.omega, m.h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, rr, st, code = api.helm_solve(op, b, tol=1e-6, precond=pc, maxit=a.maxit, net=net,
+                                             restart=a.restart if pc != "mg" else 20)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        op.close()
+        return {"iters_mean": float(it.mean()), "iters_max": int(it.max()), "converged": int((st == 0).sum()),
+                "seconds": dt}
+
+    before = iters("cnn_vu", med4)
+    op4 = api.helm_setup(t(med4.kappa2), t(med4.gamma), med4.omega, med4.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, _ = api.cnn_precond_train(net, op4, npairs=2000, batch=16, steps=200, lr=1e-4, seed=4001)
+    torch.cuda.synchronize()
+    tr = time.perf_counter() - t0
+    op4.close()
+    after = iters("cnn_vu", med4)
+    mg = iters("mg", med4)
+    print(json.dumps({"workload": "c4 retraining on the 5%-perturbed c2 medium: 2000 pairs, batch 16, "
+                                  "200 Adam steps, lr 1e-4",
+                      "pretraining": training, "retraining_seconds": tr,
+                      "retraining_loss_first": float(hist[0]), "retraining_loss_last20": float(np.mean(hist[-20:])),
+                      "before": before, "after": after, "mg": mg}))
+
+
+def main_c5(a):
+    import torch
+    from paper_2405_17696_amd import api, synth
+    nsrc = a.sources or 128
+    d = synth.config5_media(nsrc=nsrc)
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    gam = t(d["gamma"])
+    nf = len(d["omegas"])
+    n = d["kappa2_true"].size
+    # observed data: library solves in the true model at tol 1e-8
+    ops_t = [api.helm_setup(t(d["kappa2_true"]), gam, w, d["h"]) for w in d["omegas"]]
+    g = torch.zeros((nf * nsrc, n), dtype=torch.complex64, device="cuda")
+    for f in range(nf):
+        for s, k in enumerate(d["src_idx"]):
+            g[f * nsrc + s, int(k)] = 1.0 / (d["h"] * d["h"])
+    rhs_op = [f for f in range(nf) for _ in range(nsrc)]
+    u, _, _, _, _ = api.helm_solve(ops_t, g.reshape(-1), tol=1e-8, rhs_op=rhs_op, precond="mg", maxit=20000)
+    rec = torch.as_tensor(np.asarray(d["rec_idx"]), device="cuda")
+    dobs = u.reshape(nf, nsrc, n)[:, :, rec].to(torch.complex64).contiguous()
+    for o in ops_t:
+        o.close()
+    print("c5 data generated", file=sys.stderr, flush=True)
+    ops = [api.helm_setup(t(d["kappa2_init"]), gam, w, d["h"]) for w in d["omegas"]]
+    out = {}
+    for use_graph in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, grad, its, code = api.fwi_misfit_grad(ops, d["src_idx"], d["rec_idx"], dobs, tol=1e-6,
+                                                   precond="mg", maxit=a.maxit, restart=20, use_graph=use_graph)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["graph" if use_graph else "eager"] = {
+            "seconds": dt, "misfit": phi, "code": code, "solves": 2 * nf * nsrc,
+            "solves_per_s": 2 * nf * nsrc / dt, "forward_iters_mean": float(its[0].mean()),
+            "adjoint_iters_mean": float(its[1].mean()), "grad_norm": float(grad.double().norm())}
+        print(f"c5 {'graph' if use_graph else 'eager'} done in {dt:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": f"c5 FWI gradient: 512x512, {nsrc} sources, 128 receivers, {nf} frequencies, "
+                                  "MG-GMRES(20) forward + adjoint, tol 1e-6",
+                      "results": out}))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    {"c2": main_c2, "c3": main_c3, "c4": main_c4, "c5": main_c5}[a.workload](a)
 
 
 if __name__ == "__main__":
