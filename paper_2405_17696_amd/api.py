@@ -263,7 +263,7 @@ def cnn_precond_train(net: CnnNet, op: HelmOp, npairs=2000, batch=16, steps=200,
     dsz = C.c_int()
     o = L.TrainOpts(npairs, batch, steps, lr, alg2_initial, alg2_data_epochs, alg2_epochs, C.pointer(done),
                     C.pointer(dsz))
-    hist = (C.c_float * max(1, steps))()
+    hist = (C.c_float * (steps if steps > 0 else 200))()     # the library's default step count is 200
     L.check(L.load().cnn_precond_train(net.handle, op.handle, C.byref(o), int(seed), hist, _stream()))
     return np.array(hist[:done.value], dtype=np.float64), dsz.value
 

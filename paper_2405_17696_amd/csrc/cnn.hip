@@ -380,15 +380,25 @@ __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long n,
     out[t] = accumulate ? out[t] + s : s;
 }
 
-// dW[row][col] = sum_s part[s][row][col] for col < N (rows of Npad columns).
+// dW[row][col] += sum_s part[s][row][col] for col < N (rows of Npad columns);
+// four interleaved partial sums (fixed order) keep several loads in flight.
 __global__ void k_sum_wsplits(const float* __restrict__ part, int nsplit, int M, int N, int Npad,
                               float* __restrict__ out) {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)M * N) return;
     int row = (int)(t / N), col = (int)(t - (long)row * N);
-    float s = 0;
-    for (int q = 0; q < nsplit; ++q) s += part[((long)q * M + row) * Npad + col];
-    out[t] += s;
+    const long stride = (long)M * Npad;
+    const float* p = part + (long)row * Npad + col;
+    float s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int q = 0;
+    for (; q + 4 <= nsplit; q += 4) {
+        s0 += p[(long)q * stride];
+        s1 += p[(long)(q + 1) * stride];
+        s2 += p[(long)(q + 2) * stride];
+        s3 += p[(long)(q + 3) * stride];
+    }
+    for (; q < nsplit; ++q) s0 += p[(long)q * stride];
+    out[t] += (s0 + s1) + (s2 + s3);
 }
 
 // MSE: d = out - tgt; grad = 2 d / B; per-block partial of sum d^2.
@@ -757,15 +767,9 @@ static int run_backward(cnn_net* net, Arena& A, Program& P, hipStream_t s) {
                 w.P = (long)x.B * x.H * x.W;
             }
             w.Npad = (w.N + 63) / 64 * 64;
-            // about 2048 workgroups in flight
-            long tiles = (long)((w.Npad + 63) / 64) * ((w.M + 31) / 32);
-            int nsplit = (int)std::max<long>(1, std::min<long>(64, 2048 / std::max<long>(1, tiles)));
-            w.pchunk = (int)((w.P + nsplit - 1) / nsplit);
-            w.pchunk = (w.pchunk + 31) / 32 * 32;
-            nsplit = (int)((w.P + w.pchunk - 1) / w.pchunk);
-            if ((size_t)nsplit * w.M * w.Npad > A.work_elems) return fail(HELM_EINVAL, "cnn: wgrad scratch too small");
             w.part = A.work;
-            if ((rc = launch_wgrad(w, nsplit, s))) return rc;
+            int nsplit = 0;
+            if ((rc = launch_wgrad(w, (int)(A.work_elems / ((size_t)w.M * w.Npad)), s, &nsplit))) return rc;
             long nw = (long)w.M * w.N;
             hipLaunchKernelGGL(k_sum_wsplits, g1(nw), dim3(256), 0, s, A.work, nsplit, w.M, w.N, w.Npad,
                                net->grad + L.woff);
@@ -1537,10 +1541,8 @@ int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2
     wa.N = N;
     wa.Npad = Npad;
     wa.P = P;
-    wa.pchunk = (int)(((P + nsplit - 1) / nsplit + 31) / 32 * 32);
-    nsplit = (int)((P + wa.pchunk - 1) / wa.pchunk);
     wa.part = part;
-    rc = launch_wgrad(wa, nsplit, nullptr);
+    rc = launch_wgrad(wa, nsplit, nullptr, &nsplit);
     if (rc) return rc;
     hipLaunchKernelGGL(k_sum_wsplits, g1(nw), dim3(256), 0, nullptr, part, nsplit, M, N, Npad, gwd);
     // data

@@ -66,13 +66,15 @@ struct WgradArgs {
     int N;           // columns: 9*C (conv) or C (up)
     int Npad;        // N rounded up to the tile
     long P;          // reduction length (pixels)
-    int pchunk;      // pixels per split
+    int pchunk;      // pixels per split (set by launch_wgrad)
     float* part;     // [nsplit][M][Npad]
 };
 
 int launch_gemm(const GemmArgs& a, hipStream_t s);
 // enable: 1 on, 0 off (built-in rule), 2 forget the tuned shapes; -1 query only.
 int conv_autotune(int enable, int* tuned);
-int launch_wgrad(const WgradArgs& a, int nsplit, hipStream_t s);
+// Weight gradient into at most max_split partial slabs [M][Npad] at a.part;
+// *nsplit receives the number written (a.pchunk is chosen here).
+int launch_wgrad(WgradArgs a, int max_split, hipStream_t s, int* nsplit);
 
 }  // namespace helm

@@ -1023,10 +1023,130 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         }
 }
 
-int launch_wgrad(const WgradArgs& a, int nsplit, hipStream_t s) {
-    dim3 grid((a.Npad + WG_BN - 1) / WG_BN, (a.M + WG_BM - 1) / WG_BM, nsplit);
+// ------------------------------------------------------------------ weight gradient, stride-1 3x3 layers
+// dW[n][tap][c] = sum over pixels p of g[p][n] x[p + shift(tap)][c].  A block owns
+// 32 output channels (n0..), one 32-channel chunk of the input (c0..) and the
+// 16 x 16 pixel tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...  Per tile it
+// stages g transposed ([n][pixel]) and the 18 x 18 input patch transposed in
+// three column-shifted copies ([kx][c][row][col]), so that every MFMA operand
+// fragment (eight consecutive pixels of one channel) is one aligned 16-byte LDS
+// read; the reduction over pixels is the MFMA's K.  Wave w accumulates the
+// 16 x 16 block (n-tile w/2, c-tile w%2) of all nine taps; the block writes its
+// sum to part[blockIdx.x] and a fixed-order fold adds the partials.
+constexpr int WG3_GLD = HT * HT + 8;      // gT row: 256 pixels (+ pad)
+constexpr int WG3_XLD = HP * HT + 8;      // xT row: 18 patch rows x 16 columns (+ pad)
+
+__global__ __launch_bounds__(256) void k_wgrad3(WgradArgs a) {
+    __shared__ bf16 gT[32][WG3_GLD];
+    __shared__ bf16 xT[3][32][WG3_XLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.y * 32, c0 = blockIdx.z * 32;
+    const int tiles_x = (a.Wg + HT - 1) / HT, tiles_y = (a.Hg + HT - 1) / HT, tps = tiles_x * tiles_y;
+    const int ntiles = a.B * tps;
+    const int C = a.c1 + a.c2;
+    const bool s2 = c0 >= a.c1;
+    const bf16* xs = s2 ? a.a2 : a.a1;
+    const int cs = s2 ? a.c2 : a.c1, cc = s2 ? c0 - a.c1 : c0;
+    const long xbs = s2 ? a.abs2 : a.abs1;
+    const int nt = wave >> 1, ct = wave & 1;
+    f32x4 acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int b = t / tps, ty0 = ((t / tiles_x) % tiles_y) * HT, tx0 = (t % tiles_x) * HT;
+        // g tile (256 pixels x 32 channels) -> gT
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int sg = tid + q * 256, pix = sg >> 2, sub = sg & 3;
+            const int y = ty0 + (pix >> 4), x = tx0 + (pix & 15), n = n0 + sub * 8;
+            bf16x8 v = zero8();
+            if (y < a.Hg && x < a.Wg && n < a.M) {
+                const bf16* src = a.g + (((long)b * a.Hg + y) * a.Wg + x) * a.Cg + n;
+                if (n + 8 <= a.M) {
+                    v = ld8(src);
+                } else {
+                    for (int e = 0; e < 8 && n + e < a.M; ++e) v[e] = src[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gT[sub * 8 + e][pix] = v[e];
+        }
+        // input patch (18 x 18 pixels x 32 channels) -> three column-shifted transposed copies
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int sg = tid + q * 256;
+            if (sg >= HP * HP * 4) break;
+            const int pix = sg >> 2, sub = sg & 3;
+            const int py = pix / HP, px = pix - py * HP;
+            const int yi = ty0 + py - 1, xi = tx0 + px - 1;
+            const bf16x8 v = (yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi)
+                                 ? ld8(xs + b * xbs + ((long)yi * a.Wi + xi) * cs + cc + sub * 8)
+                                 : zero8();
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int col = px - kx;
+                if (col < 0 || col >= HT) continue;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xT[kx][sub * 8 + e][py * HT + col] = v[e];
+            }
+        }
+        __syncthreads();
+        // eight K-steps of 32 pixels (two tile rows)
+        const int gq = lane >> 4;
+#pragma unroll 2
+        for (int ks = 0; ks < 8; ++ks) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&gT[nt * 16 + (lane & 15)][ks * 32 + gq * 8]);
+            const int r = 2 * ks + (gq >> 1), col0 = 8 * (gq & 1);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ky = tap / 3, kx = tap % 3;
+                const bf16x8 fb =
+                    *reinterpret_cast<const bf16x8*>(&xT[kx][ct * 16 + (lane & 15)][(r + ky) * HT + col0]);
+                acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[tap], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // acc[tap][e] = dW[n = n0 + 16 nt + 4 (l/16) + e][tap][c = c0 + 16 ct + l%16]
+    float* part = a.part + (long)blockIdx.x * a.M * a.Npad;
+    const int c = c0 + ct * 16 + (lane & 15);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int n = n0 + nt * 16 + (lane >> 4) * 4 + e;
+            if (n < a.M) part[(long)n * a.Npad + tap * C + c] = acc[tap][e];
+        }
+}
+
+static bool wgrad3_ok(const WgradArgs& a) {
+    return a.mode == G_CONV && a.stride == 1 && a.c1 % 32 == 0 && a.c2 % 32 == 0 && a.c1 > 0 &&
+           a.Hg == a.Hi && a.Wg == a.Wi && a.Npad >= 9 * (a.c1 + a.c2);
+}
+
+// Weight gradient into max_split partial slabs of [M][Npad] floats; *nsplit is
+// set to the number of slabs written (the fold sums exactly those).
+int launch_wgrad(WgradArgs a, int max_split, hipStream_t s, int* nsplit) {
+    if (max_split < 1) return fail(HELM_EINVAL, "wgrad: no partial-sum space");
+    if (wgrad3_ok(a)) {
+        const int tiles = ((a.Hg + HT - 1) / HT) * ((a.Wg + HT - 1) / HT) * a.B;
+        const int nb = (a.M + 31) / 32, cb = (a.c1 + a.c2) / 32;
+        const int gx = std::max(1, std::min({tiles, max_split, std::max(1, 512 / (nb * cb))}));
+        TIMED_LAUNCH("k_wgrad", s, k_wgrad3, dim3(gx, nb, cb), dim3(256), 0, s, a);
+        HELM_CHECK_LAUNCH();
+        *nsplit = gx;
+        return HELM_OK;
+    }
+    // general path: about 2048 workgroups in flight, pixel range split into chunks
+    const long tiles = (long)((a.Npad + WG_BN - 1) / WG_BN) * ((a.M + WG_BM - 1) / WG_BM);
+    int ns = (int)std::max<long>(1, std::min<long>(std::min<long>(64, max_split), 2048 / std::max<long>(1, tiles)));
+    a.pchunk = (int)((a.P + ns - 1) / ns);
+    a.pchunk = (a.pchunk + 31) / 32 * 32;
+    ns = (int)((a.P + a.pchunk - 1) / a.pchunk);
+    dim3 grid((a.Npad + WG_BN - 1) / WG_BN, (a.M + WG_BM - 1) / WG_BM, ns);
     TIMED_LAUNCH("k_wgrad", s, k_wgrad, grid, dim3(256), 0, s, a);
     HELM_CHECK_LAUNCH();
+    *nsplit = ns;
     return HELM_OK;
 }
 
