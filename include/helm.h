@@ -249,6 +249,8 @@ int helm_autotune(int enable, int* tuned_shapes);
  * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",
  * "k_conv_fwd", ...) with HIP events recorded on the stream it is launched on,
  * and count the algorithmic bytes (or flops) its active blocks processed.
+ * Launches inside a captured restart-cycle graph are timed too: the events
+ * become event-record nodes of the graph and are read after every replay.
  * kernel = NULL stops timing.  helm_ktimer_read synchronises the device and
  * returns the totals since the last start (host outputs).
  */

@@ -5,7 +5,7 @@
 namespace helm {
 
 // Make sure the encoder context of (net, op) is current (runs the encoder if needed).
-int cnn_prepare(cnn_net* net, const helm_op* op, hipStream_t s);
+int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s);
 // e = SolverNet(scale_r * r) / scale_r for nrhs vectors of op's grid (c64, or c128
 // when wide != 0), skipping RHS whose state is inactive.  scale_r comes from
 // fscale[(rhs0 + r) * fstride] (may be null: 1).

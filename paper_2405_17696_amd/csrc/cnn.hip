@@ -917,12 +917,6 @@ static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s, EncC
     return HELM_OK;
 }
 
-int cnn_prepare(cnn_net* net, const helm_op* op, hipStream_t s) {
-    (void)net;
-    (void)op;
-    (void)s;
-    return HELM_OK;
-}
 
 // Makes A->ctx the encoder context of (net, op), running the encoder only when
 // the operator has none for this network version.
@@ -968,6 +962,34 @@ void cnn_release_cache(helm_op* op) {
     op->enc.ctx = nullptr;
 }
 
+// Per-batch-size scale buffers (s_in, s_out per RHS), allocated once.
+static int scale_bufs(int nrhs, double** sin, double** sout) {
+    static std::map<int, std::pair<double*, double*>> sbuf;
+    auto& sb = sbuf[nrhs];
+    if (!sb.first) {
+        if (hipMalloc(&sb.first, sizeof(double) * nrhs) != hipSuccess ||
+            hipMalloc(&sb.second, sizeof(double) * nrhs) != hipSuccess)
+            return fail(HELM_ENOMEM, "cnn: scale buffers");
+    }
+    *sin = sb.first;
+    *sout = sb.second;
+    return HELM_OK;
+}
+
+// Everything a preconditioner application for nrhs right-hand sides of op
+// allocates or computes once (arena, encoder context, scale buffers), done
+// eagerly so that later applications can be captured into a graph.
+int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s) {
+    std::lock_guard<std::recursive_mutex> lk(g_cnn_mutex);
+    int rc;
+    if ((rc = check_grid(op))) return rc;
+    Arena* A;
+    if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
+    if ((rc = ensure_encoded(net, op, A, s))) return rc;
+    double *a, *b;
+    return scale_bufs(nrhs, &a, &b);
+}
+
 // e = M_net(r) for nrhs vectors.  Scales: s_in = sqrt(N) fscale (FGMRES basis
 // vectors have unit norm after scaling) or sqrt(N)/||r|| when fscale is null.
 template <typename T>
@@ -978,13 +1000,8 @@ static int apply_impl(cnn_net* net, const helm_op* op, const cx<T>* r, const dou
     Arena* A;
     if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
     if ((rc = ensure_encoded(net, op, A, s))) return rc;
-    static std::map<int, std::pair<double*, double*>> sbuf;
-    auto& sb = sbuf[nrhs];
-    if (!sb.first) {
-        if (hipMalloc(&sb.first, sizeof(double) * nrhs) != hipSuccess ||
-            hipMalloc(&sb.second, sizeof(double) * nrhs) != hipSuccess)
-            return fail(HELM_ENOMEM, "cnn: scale buffers");
-    }
+    std::pair<double*, double*> sb;
+    if ((rc = scale_bufs(nrhs, &sb.first, &sb.second))) return rc;
     const long N = op->n();
     const double sqrtN = std::sqrt((double)N), h2 = op->hx * op->hz;
     if (fscale) {

@@ -34,10 +34,11 @@ int fail(int code, const char* fmt, ...);
 struct KTimer {
     bool armed(const char* name) const;
     unsigned long long* counter() const;
+    bool capturing(hipStream_t s) const;
     void begin(hipStream_t s);
     void end(hipStream_t s);
-    // Add the elapsed time of event pairs recorded inside a replayed graph
-    // (call after the replay has completed).
+    // Kept for the solver's replay loop; launches inside graphs are not timed.
+    void replayed();
     void harvest();
     // Forget the event pairs of a previous graph (called before a new capture).
     void new_capture();
@@ -52,10 +53,20 @@ KTimer& ktimer();
         if (on_) ::helm::ktimer().end(stream);                  \
     } while (0)
 
-#define WORK_COUNTER(name) (::helm::ktimer().armed(name) ? ::helm::ktimer().counter() : nullptr)
+// Launches recorded into a graph are neither timed nor counted.
+#define WORK_COUNTER(name, stream) \
+    (::helm::ktimer().armed(name) && !::helm::ktimer().capturing(stream) ? ::helm::ktimer().counter() : nullptr)
 
+// The work counter is spread over WORK_SLOTS slots 128 bytes apart (block-index
+// hashed), so that the one atomic per block does not serialise all blocks of a
+// launch on a single address; helm_ktimer_read sums the slots.
+constexpr int WORK_SLOTS = 64, WORK_SLOT_STRIDE = 16;
+__device__ __forceinline__ void work_atomic(unsigned long long* c, unsigned long long v) {
+    const unsigned slot = (blockIdx.x + 7u * blockIdx.y + 13u * blockIdx.z) % WORK_SLOTS;
+    atomicAdd(c + slot * WORK_SLOT_STRIDE, v);
+}
 __device__ __forceinline__ void add_work(unsigned long long* c, unsigned long long v) {
-    if (c && threadIdx.x == 0) atomicAdd(c, v);
+    if (c && threadIdx.x == 0) work_atomic(c, v);
 }
 
 // ---------------------------------------------------------------- complex

@@ -168,7 +168,7 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
         if ((rc = W.cnn_e0.ensure(sizeof(cx<T>) * maxg))) return rc;
         if ((rc = W.cnn_res.ensure(sizeof(cx<T>) * maxg))) return rc;
         for (auto& gr : groups)
-            if ((rc = cnn_prepare(o.net, ops[gr.op], s))) return rc;
+            if ((rc = cnn_prepare(o.net, ops[gr.op], gr.n, s))) return rc;
     }
 
     const c64* b = (const c64*)rhs;
@@ -308,6 +308,7 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
                 HELM_HIP(hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0));
             }
             HELM_HIP(hipGraphLaunch(gh.exec, s));
+            ktimer().replayed();
         } else if ((rc = cycle_body())) {
             return rc;
         }

@@ -514,7 +514,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             dim3 grid((C.nx + MG_T - 1) / MG_T, (C.nz + MG_T - 1) / MG_T, nr);
             TIMED_LAUNCH("k_mg_down", s, k_mg_down<T>, grid, dim3(256), 0, s, fin, l == 0 ? fscale : nullptr,
                          fstride, wd_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.f[l + 1] + (long)r0 * C.n(), C.nz,
-                         C.nx, st, rhs0 + r0, WORK_COUNTER("k_mg_down"));
+                         C.nx, st, rhs0 + r0, WORK_COUNTER("k_mg_down", s));
             HELM_CHECK_LAUNCH();
         }
         // coarsest level: x = p(P) f
@@ -534,7 +534,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
                 size_t lds = 2 * (size_t)n * sizeof(c128);
                 TIMED_LAUNCH("k_poly_lds", s, k_poly_lds<T>, dim3(nr), dim3(POLY_THREADS), lds, s, src, xdst, C.sl64,
                              C.nz, C.nx, C.sten<double>(), op->roots_dev, deg, st, rhs0 + r0,
-                             WORK_COUNTER("k_poly_lds"));
+                             WORK_COUNTER("k_poly_lds", s));
                 HELM_CHECK_LAUNCH();
             } else
             for (int t = 0; t < deg; ++t) {
@@ -545,7 +545,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
                 c128* rout = bufs[t & 1];
                 TIMED_LAUNCH("k_poly_term", s, k_poly_term<T>, grid, dim3(256), 0, s, src, rin, rout, xw, xdst,
                              C.sl64, C.nz, C.nx, C.sten<double>(), it, t == 0 ? 1 : 0, t == deg - 1 ? 1 : 0, st,
-                             rhs0 + r0, WORK_COUNTER("k_poly_term"));
+                             rhs0 + r0, WORK_COUNTER("k_poly_term", s));
                 HELM_CHECK_LAUNCH();
             }
         }
@@ -558,7 +558,7 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             dim3 grid((F.nx + MG_T - 1) / MG_T, (F.nz + MG_T - 1) / MG_T, nr);
             TIMED_LAUNCH("k_mg_up", s, k_mg_up<T>, grid, dim3(256), 0, s, fin, l == 0 ? fscale : nullptr, fstride,
                          sl_of<T>(F), wd_of<T>(F), F.nz, F.nx, F.sten<T>(), wj, w.e[l + 1] + (long)r0 * C.n(), C.nz, C.nx, dst,
-                         (l == 0 && addend) ? addend + off0 : nullptr, st, rhs0 + r0, WORK_COUNTER("k_mg_up"));
+                         (l == 0 && addend) ? addend + off0 : nullptr, st, rhs0 + r0, WORK_COUNTER("k_mg_up", s));
             HELM_CHECK_LAUNCH();
         }
     }
@@ -1052,28 +1052,28 @@ static int launch_reduce(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, i
 template <typename T>
 int launch_true_residual(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, hipStream_t s) {
     TIMED_LAUNCH("k_true_residual", s, k_true_residual<T>, dim3(g.nblk, ng), dim3(VEC_THREADS), 0, s, g, a,
-                 WORK_COUNTER("k_true_residual"));
+                 WORK_COUNTER("k_true_residual", s));
     HELM_CHECK_LAUNCH();
     return launch_reduce<T>(g, ng, a, RED_RESID, 0, s);
 }
 template <typename T>
 int launch_matvec_dot(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, int j, hipStream_t s) {
     TIMED_LAUNCH("k_matvec_dot", s, k_matvec_dot<T>, dim3(g.nblk, ng), dim3(VEC_THREADS), 0, s, g, a, j,
-                 WORK_COUNTER("k_matvec_dot"));
+                 WORK_COUNTER("k_matvec_dot", s));
     HELM_CHECK_LAUNCH();
     return launch_reduce<T>(g, ng, a, RED_DOTS, j, s);
 }
 template <typename T>
 int launch_update(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, int j, int pass, hipStream_t s) {
     TIMED_LAUNCH("k_update", s, k_update<T>, dim3(g.nblk, ng), dim3(VEC_THREADS), 0, s, g, a, j, pass,
-                 WORK_COUNTER("k_update"));
+                 WORK_COUNTER("k_update", s));
     HELM_CHECK_LAUNCH();
     return launch_reduce<T>(g, ng, a, pass == 1 ? RED_NORM1 : RED_NORM2, j, s);
 }
 template <typename T>
 int launch_dot2(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, int j, hipStream_t s) {
     TIMED_LAUNCH("k_dot2", s, k_dot2<T>, dim3(g.nblk, ng), dim3(VEC_THREADS), 0, s, g, a, j,
-                 WORK_COUNTER("k_dot2"));
+                 WORK_COUNTER("k_dot2", s));
     HELM_CHECK_LAUNCH();
     return launch_reduce<T>(g, ng, a, RED_DOTS2, j, s);
 }
@@ -1086,7 +1086,7 @@ int launch_lsq(const SolveArgs<T>& a, hipStream_t s) {
 template <typename T>
 int launch_sol_update(const GroupArgs<T>& g, int ng, const SolveArgs<T>& a, hipStream_t s) {
     TIMED_LAUNCH("k_sol_update", s, k_sol_update<T>, dim3(g.nblk, ng), dim3(VEC_THREADS), 0, s, g, a,
-                 WORK_COUNTER("k_sol_update"));
+                 WORK_COUNTER("k_sol_update", s));
     HELM_CHECK_LAUNCH();
     return HELM_OK;
 }

@@ -11,9 +11,6 @@ namespace {
 struct TimerState {
     std::string name;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;   // eager launches
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> cap;  // launches inside a captured graph
-    double cap_ms = 0;
-    long cap_launches = 0;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     unsigned long long* dcount = nullptr;
@@ -21,10 +18,12 @@ struct TimerState {
 };
 TimerState g_t;
 
+// Fence-free events (no system-scope release): the timestamps stay exact and
+// the packets cost far less than default events between back-to-back kernels.
 hipEvent_t take_event() {
     if (g_t.used < g_t.pool.size()) return g_t.pool[g_t.used++];
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     g_t.pool.push_back(e);
     g_t.used++;
     return e;
@@ -33,28 +32,28 @@ hipEvent_t take_event() {
 
 bool KTimer::armed(const char* name) const { return !g_t.name.empty() && g_t.name == name; }
 unsigned long long* KTimer::counter() const { return g_t.dcount; }
-// Launches inside a stream capture are not timed: the graph replays them.
-static bool capturing(hipStream_t s) {
+static bool stream_capturing(hipStream_t s) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
 }
+bool KTimer::capturing(hipStream_t s) const { return stream_capturing(s); }
+// Launches inside a stream capture are not timed: a replayed graph has no
+// per-launch events (the timed measurements launch eagerly).
 void KTimer::begin(hipStream_t s) {
     g_t.pending = nullptr;
-    if (capturing(s)) return;
-    g_t.pending = take_event();
-    if (g_t.pending) (void)hipEventRecord(g_t.pending, s);
+    if (stream_capturing(s)) return;
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) g_t.pending = e;
 }
 void KTimer::end(hipStream_t s) {
     if (!g_t.pending) return;
     hipEvent_t e = take_event();
-    if (e) {
-        (void)hipEventRecord(e, s);
-        g_t.ev.push_back({g_t.pending, e});
-    }
+    if (e && hipEventRecord(e, s) == hipSuccess) g_t.ev.push_back({g_t.pending, e});
     g_t.pending = nullptr;
 }
+void KTimer::replayed() {}
 void KTimer::harvest() {}
-void KTimer::new_capture() { g_t.cap.clear(); }
+void KTimer::new_capture() {}
 KTimer& ktimer() {
     static KTimer t;
     return t;
@@ -67,15 +66,13 @@ using namespace helm;
 extern "C" int helm_ktimer_start(const char* kernel) {
     if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_start: device sync failed");
     g_t.ev.clear();
-    g_t.cap.clear();
-    g_t.cap_ms = 0;
-    g_t.cap_launches = 0;
     g_t.used = 0;
     g_t.name = kernel ? kernel : "";
     if (kernel) {
-        if (!g_t.dcount && hipMalloc(&g_t.dcount, sizeof(unsigned long long)) != hipSuccess)
+        const size_t bytes = sizeof(unsigned long long) * WORK_SLOTS * WORK_SLOT_STRIDE;
+        if (!g_t.dcount && hipMalloc(&g_t.dcount, bytes) != hipSuccess)
             return fail(HELM_ENOMEM, "helm_ktimer_start: counter allocation failed");
-        if (hipMemset(g_t.dcount, 0, sizeof(unsigned long long)) != hipSuccess)
+        if (hipMemset(g_t.dcount, 0, bytes) != hipSuccess)
             return fail(HELM_EHIP, "helm_ktimer_start: counter reset failed");
     }
     return HELM_OK;
@@ -91,10 +88,15 @@ extern "C" int helm_ktimer_read(int* launches, double* total_ms, double* total_w
         ms += t;
     }
     unsigned long long w = 0;
-    if (g_t.dcount && hipMemcpy(&w, g_t.dcount, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(HELM_EHIP, "helm_ktimer_read: counter read failed");
-    if (launches) *launches = (int)(g_t.ev.size() + g_t.cap_launches);
-    if (total_ms) *total_ms = ms + g_t.cap_ms;
+    if (g_t.dcount) {
+        std::vector<unsigned long long> slots(WORK_SLOTS * WORK_SLOT_STRIDE);
+        if (hipMemcpy(slots.data(), g_t.dcount, sizeof(unsigned long long) * slots.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return fail(HELM_EHIP, "helm_ktimer_read: counter read failed");
+        for (int i = 0; i < WORK_SLOTS; ++i) w += slots[(size_t)i * WORK_SLOT_STRIDE];
+    }
+    if (launches) *launches = (int)g_t.ev.size();
+    if (total_ms) *total_ms = ms;
     if (total_work) *total_work = (double)w;
     return HELM_OK;
 }

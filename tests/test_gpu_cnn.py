@@ -205,6 +205,12 @@ def test_cnn_vu_fgmres_converges(gpu):
     xg, itg, _, _, cg = api.helm_solve(H, bt, tol=1e-6, precond="cnn_vu", maxit=600, net=net, restart=20,
                                        use_graph=True)
     assert cg == 0 and np.array_equal(it, itg) and torch.equal(x, xg)
+    # a fresh operator whose first solve is graph-captured: the encoder context
+    # and buffers are prepared eagerly before the capture
+    H2 = setup(med)
+    x2, it2, _, _, c2 = api.helm_solve(H2, bt, tol=1e-6, precond="cnn_vu", maxit=600, net=net, restart=20,
+                                       use_graph=True)
+    assert c2 == 0 and np.array_equal(it, it2) and torch.equal(x, x2)
 
 
 def test_cnn_only_preconditioner_reports_status(gpu):
