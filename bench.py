@@ -68,6 +68,23 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic():
+    """HBM bytes per launch of the convolution family from the committed counter
+    summary, or None when the kernels changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "conv_family_hbm_traffic_256x256_32rhs.md")
+    src = os.path.join(ROOT, "paper_2405_17696_amd", "csrc", "conv.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "conv_source_sha256_16"))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if fields.get("conv_source_sha256_16") != cur:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def kernel_roofline(api_lib, name):
     import ctypes as C
     n = C.c_int()
@@ -219,7 +236,8 @@ def main_c2(a):
     if roof and kernel == "k_conv":
         ach = roof["achieved"] / 1e3          # work counter holds flops: GFLOP/s -> TFLOP/s
         roofline = {"bound": "mfma", "kernel": roof["kernel"], "achieved": ach, "peak": BF16_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS, "traffic": None,
+                    "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+                    "traffic": measured_traffic() if precond == "cnn_vu" and restart == 10 else None,
                     "avg_us": roof["avg_us"], "launches": roof["launches"],
                     "flops_per_launch": roof["work_per_launch"]}
     elif roof:
