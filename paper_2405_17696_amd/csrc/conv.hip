@@ -30,13 +30,17 @@ __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<
 struct Pix {
     int b, y, x;
 };
+// 32-bit unsigned divisions: every row index of these grids fits in 31 bits
+// (the launchers reject larger grids), and 64-bit division is a long software
+// sequence on the GPU.
 __device__ __forceinline__ Pix pix_of(long m, int Ho, int Wo) {
     Pix p;
-    long hw = (long)Ho * Wo;
-    p.b = (int)(m / hw);
-    long r = m - (long)p.b * hw;
-    p.y = (int)(r / Wo);
-    p.x = (int)(r - (long)p.y * Wo);
+    const unsigned mu = (unsigned)m, hw = (unsigned)Ho * (unsigned)Wo;
+    const unsigned b = mu / hw, r = mu - b * hw;
+    const unsigned y = r / (unsigned)Wo;
+    p.b = (int)b;
+    p.y = (int)y;
+    p.x = (int)(r - y * (unsigned)Wo);
     return p;
 }
 
@@ -639,8 +643,8 @@ __global__ __launch_bounds__(256) void k_conv3_smallc(GemmArgs a, unsigned long 
         work_atomic(wc, 2ull * cnt * 8 * K9);
     }
     for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < nq; q += (long)gridDim.x * 256) {
-        const long m = q / G;
-        const int n8 = (int)(q - m * G) * 8;
+        const long m = (long)((unsigned)q / (unsigned)G);
+        const int n8 = (int)((unsigned)q - (unsigned)m * (unsigned)G) * 8;
         const Pix p = pix_of(m, a.Ho, a.Wo);
         if (a.st && !(a.st[a.rhs0 + p.b].active && !a.st[a.rhs0 + p.b].cycdone)) continue;
         float v[8];
@@ -895,6 +899,8 @@ int tune(const GemmArgs& a, hipStream_t s, int* best) {
 
 int launch_gemm(const GemmArgs& a, hipStream_t s) {
     if (a.K % KC != 0) return fail(HELM_EINVAL, "gemm: K=%d not a multiple of %d", a.K, KC);
+    if (a.M * (long)std::max(1, a.N) >= (1L << 31) || (long)a.B * a.Hi * a.Wi >= (1L << 31))
+        return fail(HELM_EINVAL, "gemm: grid of %ld rows too large for 32-bit pixel indexing", a.M);
     if (a.M <= 0 || a.N <= 0) return HELM_OK;
     int ck = ck_default(a);
     const bool tunable = (a.epi == E_FWD || a.epi == E_UPFWD) && a.out != nullptr;

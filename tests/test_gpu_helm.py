@@ -110,12 +110,12 @@ def test_solve_batch_and_edges(gpu):
     x, it, rr, st, code = api.helm_solve(H, to_dev(b), tol=1e-8, precond="mg", restart=20, maxit=800)
     x = x.cpu().numpy()
     coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
-    rel = op.relres(coef, x, b.astype(np.complex128), med.h, med.h)
+    nz_rows = [0, 2, 3, 4]                   # the relative residual of b = 0 is undefined
+    rel = op.relres(coef, x[nz_rows], b[nz_rows].astype(np.complex128), med.h, med.h)
     assert code == 0
     assert np.all(st == 0)
     assert np.abs(x[1]).max() == 0 and it[1] == 0
-    for r in (0, 2, 3, 4):
-        assert rel[r] <= 1e-8
+    assert np.all(rel <= 1e-8)
     # iteration cap -> soft failure with status per RHS
     x, it, rr, st, code = api.helm_solve(H, to_dev(b[:1]), tol=1e-10, precond="mg", maxit=3)
     assert code == 1 and st[0] == 1 and it[0] == 3
