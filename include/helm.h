@@ -182,6 +182,12 @@ int cnn_layer_forward(int kind, int stride, int B, int H, int W, int c1, int c2,
 int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2, int bcast2, int cout,
                        const float* x1, const float* x2, const float* w, const float* y, int relu, const float* gout,
                        float* gx1, float* gx2, float* gw, float* gb);
+/* Fused 32-channel residual block out = x + conv2(ReLU(conv1(x) + b1)) + b2
+ * (stride 1, zero padding; weights [32][3][3][32], FP32 HOST buffers, x and
+ * out [B][H][W][32], inputs rounded to BF16, out rounded to BF16), the kernel
+ * that inference uses for the networks' first-level residual blocks. */
+int cnn_layer_resblock(int B, int H, int W, const float* x, const float* w1, const float* b1, const float* w2,
+                       const float* b2, float* out);
 
 typedef struct {
     int npairs;            /* plain training: pairs generated by eq. (4.3); <= 0: 2000 */

@@ -79,6 +79,8 @@ SIGNATURES = {
     "cnn_adam_step": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "cnn_make_pairs": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cnn_alg2_epoch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "cnn_layer_resblock": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
     "helm_autotune": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
     "fwi_misfit_grad": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
                                   C.POINTER(C.c_int), C.c_int, C.c_void_p, C.c_double, C.POINTER(SolveOpts),

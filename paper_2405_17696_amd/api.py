@@ -277,6 +277,19 @@ def _vp(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
+def cnn_layer_resblock(x, w1, b1, w2, b2):
+    """Fused 32-channel residual block through the library kernel; host float arrays, NHWC."""
+    import numpy as np
+    x = _f32(x)
+    B, H, Wd, Cc = x.shape
+    if Cc != 32:
+        raise ValueError("the fused residual block takes 32 channels")
+    out = np.empty_like(x)
+    L.check(L.load().cnn_layer_resblock(B, H, Wd, _vp(x), _vp(_f32(w1)), _vp(_f32(b1)), _vp(_f32(w2)),
+                                        _vp(_f32(b2)), _vp(out)))
+    return out
+
+
 def cnn_layer_forward(kind, stride, x1, w, b, x2=None, bcast2=False, resid=None, relu=True):
     """One layer through the library kernels; host float arrays, NHWC."""
     import numpy as np

@@ -639,8 +639,48 @@ static const Tens& tens_of(const Arena& A, const Program& P, int id) {
     return P.t[id];
 }
 
+// Ops oi, oi+1 form a 32-channel residual block y = x + conv(ReLU(conv(x))) that
+// inference runs as one fused kernel (the intermediate stays in LDS).
+static bool fusable_resblock(const cnn_net* net, const Arena& A, const Program& P, size_t oi) {
+    if (A.train || oi + 1 >= P.ops.size()) return false;
+    const Op& a = P.ops[oi];
+    const Op& b = P.ops[oi + 1];
+    if (a.kind != OP_CONV || b.kind != OP_CONV || a.stride != 1 || b.stride != 1) return false;
+    if (!a.relu || b.relu || a.resid >= 0 || a.in2 != -1 || b.in2 != -1) return false;
+    if (b.in1 != a.out || b.resid != a.in1 || a.in1 < 0) return false;
+    const Tens& x = P.t[a.in1];
+    const Tens& h = P.t[a.out];
+    const Tens& y = P.t[b.out];
+    return x.C == 32 && h.C == 32 && y.C == 32 && net->layers[a.layer].K >= 288 && net->layers[b.layer].K >= 288;
+}
+
 static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState* st, int rhs0, hipStream_t s) {
-    for (const Op& op : P.ops) {
+    for (size_t oi = 0; oi < P.ops.size(); ++oi) {
+        const Op& op = P.ops[oi];
+        if (fusable_resblock(net, A, P, oi)) {
+            const Op& o2 = P.ops[oi + 1];
+            const LayerDesc& L1 = net->layers[op.layer];
+            const LayerDesc& L2 = net->layers[o2.layer];
+            const Tens& x = P.t[op.in1];
+            ResArgs r{};
+            r.x = x.d;
+            r.B = x.B;
+            r.H = x.H;
+            r.W = x.W;
+            r.w1 = net->wb + L1.wb_off;
+            r.K1 = L1.K;
+            r.b1 = net->master + L1.boff;
+            r.w2 = net->wb + L2.wb_off;
+            r.K2 = L2.K;
+            r.b2 = net->master + L2.boff;
+            r.out = P.t[o2.out].d;
+            r.st = (&P == &A.sol) ? st : nullptr;
+            r.rhs0 = rhs0;
+            int rc = launch_resblock32(r, s);
+            if (rc) return rc;
+            ++oi;
+            continue;
+        }
         const LayerDesc& L = net->layers[op.layer];
         const Tens& x = tens_of(A, P, op.in1);
         Tens& y = P.t[op.out];
@@ -1411,6 +1451,46 @@ int cnn_forward(cnn_net_t n, helm_op_t op, const float* rin, float* out, int B, 
     return HELM_OK;
 }
 
+
+int cnn_layer_resblock(int B, int H, int W, const float* x, const float* w1, const float* b1, const float* w2,
+                       const float* b2, float* out) {
+    if (B <= 0 || H <= 0 || W <= 0 || !x || !w1 || !b1 || !w2 || !b2 || !out)
+        return fail(HELM_EINVAL, "cnn_layer_resblock: bad arguments");
+    Keep k;
+    const long nw = 32L * 9 * 32, nx = (long)B * H * W * 32;
+    const int K = pad32(9 * 32), Kt = pad32(9 * 32);
+    float* w1d = dev_copy(w1, nw, k.p);
+    float* w2d = dev_copy(w2, nw, k.p);
+    float* b1d = dev_copy(b1, 32, k.p);
+    float* b2d = dev_copy(b2, 32, k.p);
+    bf16* f1 = dev_copy<bf16>(nullptr, 32L * K, k.p);
+    bf16* f2 = dev_copy<bf16>(nullptr, 32L * K, k.p);
+    bf16* t1 = dev_copy<bf16>(nullptr, 32L * Kt, k.p);
+    bf16* t2 = dev_copy<bf16>(nullptr, 32L * Kt, k.p);
+    bf16* xd = dev_bf16(x, nx, k.p);
+    bf16* yd = dev_copy<bf16>(nullptr, nx, k.p);
+    if (!w1d || !w2d || !b1d || !b2d || !f1 || !f2 || !t1 || !t2 || !xd || !yd) return fail(HELM_ENOMEM, "buffers");
+    hipLaunchKernelGGL(k_refresh_conv, g1(32L * K), dim3(256), 0, nullptr, w1d, 32, 32, K, Kt, f1, t1);
+    hipLaunchKernelGGL(k_refresh_conv, g1(32L * K), dim3(256), 0, nullptr, w2d, 32, 32, K, Kt, f2, t2);
+    ResArgs r{};
+    r.x = xd;
+    r.B = B;
+    r.H = H;
+    r.W = W;
+    r.w1 = f1;
+    r.K1 = K;
+    r.b1 = b1d;
+    r.w2 = f2;
+    r.K2 = K;
+    r.b2 = b2d;
+    r.out = yd;
+    int rc = launch_resblock32(r, nullptr);
+    if (rc) return rc;
+    std::vector<bf16> hb(nx);
+    HELM_HIP(hipMemcpy(hb.data(), yd, sizeof(bf16) * nx, hipMemcpyDeviceToHost));
+    for (long i = 0; i < nx; ++i) out[i] = (float)hb[i];
+    return HELM_OK;
+}
 
 int cnn_layer_forward(int kind, int stride, int B, int H, int W, int c1, int c2, int bcast2, int cout,
                       const float* x1, const float* x2, const float* w, const float* b, const float* resid, int relu,

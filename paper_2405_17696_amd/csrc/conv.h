@@ -71,6 +71,23 @@ struct WgradArgs {
 };
 
 int launch_gemm(const GemmArgs& a, hipStream_t s);
+
+// Fused residual block y = x + conv2(ReLU(conv1(x) + b1)) + b2, 32 channels,
+// stride 1 (inference); weights in the forward layout [32][K] (k = tap*32 + c).
+struct ResArgs {
+    const bf16* x;       // [B][H][W][32], also the residual
+    int B, H, W;
+    const bf16* w1;
+    int K1;
+    const float* b1;
+    const bf16* w2;
+    int K2;
+    const float* b2;
+    bf16* out;           // [B][H][W][32]
+    const RhsState* st;  // optional: skip samples whose RHS is inactive
+    int rhs0;
+};
+int launch_resblock32(const ResArgs& a, hipStream_t s);
 // enable: 1 on, 0 off (built-in rule), 2 forget the tuned shapes; -1 query only.
 int conv_autotune(int enable, int* tuned);
 // Weight gradient into at most max_split partial slabs [M][Npad] at a.part;

@@ -694,15 +694,6 @@ static bool smallc_ok(const GemmArgs& a) {
            a.N % 8 == 0 && a.N <= SC_MAXN && a.K >= 9 * a.c1;
 }
 
-// The halo kernels apply when every source has a multiple of 32 channels.
-static bool halo_ok(const GemmArgs& a) {
-    if (!(a.gmode == G_CONV || a.gmode == G_CONVT) || a.stride != 1) return false;
-    if (a.c1 % HC || a.c2 % HC) return false;
-    if (a.gmode == G_CONV && a.epi != E_FWD) return false;
-    if (a.gmode == G_CONVT && a.epi != E_ACC) return false;
-    return a.K >= 9 * (a.c1 + a.c2);
-}
-
 // Resident blocks of a kernel on the whole device (cached per kernel).
 template <typename K>
 static int resident_blocks(K kernel, int& cache) {
@@ -715,6 +706,167 @@ static int resident_blocks(K kernel, int& cache) {
     cache = per_cu * cus;
     return cache;
 }
+
+// ------------------------------------------------------------------ fused 32-channel residual block
+// y = x + W2 * ReLU(W1 * x + b1) + b2 for 32 channels (the networks' first
+// level, where the convolutions are bound by HBM traffic).  A block keeps both
+// weight sets in LDS and walks over 14 x 14 output tiles: it stages the 18 x 18
+// input patch, computes h = ReLU(W1 * x + b1) on the surrounding 16 x 16 grid
+// (zero outside the image, the padding of the second convolution), writes h
+// back into the patch buffer with a zero border, and runs the second
+// convolution there; the residual is read from the staged input.  The
+// intermediate h never reaches HBM.
+constexpr int RT = HT - 2;   // output tile edge (14)
+
+__global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long long* wc) {
+    __shared__ bf16 Ps[HP * HP][HLD];
+    __shared__ bf16 W1s[9][32][HLD];
+    __shared__ bf16 W2s[9][32][HLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (a.W + RT - 1) / RT, tiles_y = (a.H + RT - 1) / RT, tps = tiles_x * tiles_y;
+    const int ntiles = a.B * tps;
+    auto next_tile = [&](int t) {
+        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+            t += gridDim.x;
+        return t;
+    };
+    int t = next_tile(blockIdx.x);
+    if (t >= ntiles) return;   // the same decision for every thread of the block
+    for (int sg = tid; sg < 9 * 32 * 4; sg += 256) {
+        const int row = sg >> 2, sub = sg & 3, tap = row >> 5, n = row & 31;
+        *reinterpret_cast<bf16x8*>(&W1s[tap][n][sub * 8]) = ld8(a.w1 + (long)n * a.K1 + tap * 32 + sub * 8);
+        *reinterpret_cast<bf16x8*>(&W2s[tap][n][sub * 8]) = ld8(a.w2 + (long)n * a.K2 + tap * 32 + sub * 8);
+    }
+    // the input patch of a tile with output origin (oy0, ox0) starts at (oy0 - 2, ox0 - 2);
+    // HaloStage loads the patch of a 16 x 16 grid at origin (ty0, tx0) from (ty0 - 1, tx0 - 1)
+    GemmArgs g{};
+    g.a1 = a.x;
+    g.c1 = 32;
+    g.abs1 = (long)a.H * a.W * 32;
+    g.Hi = a.H;
+    g.Wi = a.W;
+    HaloStage<32> st;
+    auto origin = [&](int tt, int& b, int& oy0, int& ox0) {
+        b = tt / tps;
+        oy0 = ((tt / tiles_x) % tiles_y) * RT;
+        ox0 = (tt % tiles_x) * RT;
+    };
+    int b, oy0, ox0;
+    origin(t, b, oy0, ox0);
+    st.load(g, tid, b, oy0 - 1, ox0 - 1, 0, 0, false);
+    unsigned long long work = 0;
+    typedef __bf16 bf16x4r __attribute__((ext_vector_type(4)));
+    while (true) {
+        origin(t, b, oy0, ox0);
+        st.store(Ps, W1s, tid, false);
+        __syncthreads();
+        const int tn = next_tile(t + gridDim.x);
+        if (tn < ntiles) {
+            int bn, yn, xn;
+            origin(tn, bn, yn, xn);
+            st.load(g, tid, bn, yn - 1, xn - 1, 0, 0, false);
+        }
+        // stage A: h on the 16 x 16 grid at image origin (oy0 - 1, ox0 - 1)
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        halo_mma<32, 0>(Ps, W1s, 0, acc, lane, wave);
+        // residual x at the same grid positions (patch offset +1) before the patch is overwritten
+        const int px = lane & 15;
+        bf16x4r res[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                res[i][j] = *reinterpret_cast<const bf16x4r*>(
+                    &Ps[(wave * 4 + i + 1) * HP + px + 1][j * 16 + (lane >> 4) * 4]);
+        __syncthreads();
+        // h (ReLU, zero outside the image) into the patch buffer at offset +1, zero border
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = wave * 4 + i;
+            const int yi = oy0 - 1 + py, xi = ox0 - 1 + px;
+            const bool in = yi >= 0 && yi < a.H && xi >= 0 && xi < a.W;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int n = j * 16 + (lane >> 4) * 4;
+                bf16x4r hv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = acc[i][j][e] + a.b1[n + e];
+                    hv[e] = (bf16)(in && v > 0.f ? v : 0.f);
+                }
+                *reinterpret_cast<bf16x4r*>(&Ps[(py + 1) * HP + px + 1][n]) = hv;
+            }
+        }
+        for (int q = tid; q < (4 * HP - 4) * 4; q += 256) {   // the 68 border pixels x 4 segments
+            const int bp = q >> 2, sub = q & 3;
+            int pyb, pxb;
+            if (bp < HP) {
+                pyb = 0;
+                pxb = bp;
+            } else if (bp < 2 * HP) {
+                pyb = HP - 1;
+                pxb = bp - HP;
+            } else {
+                const int r = bp - 2 * HP;   // 0 .. 2*(HP-2)-1
+                pyb = 1 + (r >> 1);
+                pxb = (r & 1) ? HP - 1 : 0;
+            }
+            *reinterpret_cast<bf16x8*>(&Ps[pyb * HP + pxb][sub * 8]) = zero8();
+        }
+        __syncthreads();
+        // stage B: second convolution over h; grid positions 1 .. 14 are the outputs
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        halo_mma<32, 0>(Ps, W2s, 0, acc, lane, wave);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = wave * 4 + i;
+            const int y = oy0 - 1 + py, x = ox0 - 1 + px;
+            if (py < 1 || py > RT || px < 1 || px > RT || y >= a.H || x >= a.W) continue;
+            const long m = ((long)b * a.H + y) * a.W + x;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int n = j * 16 + (lane >> 4) * 4;
+                bf16x4r o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (bf16)(acc[i][j][e] + a.b2[n + e] + (float)res[i][j][e]);
+                *reinterpret_cast<bf16x4r*>(a.out + m * 32 + n) = o;
+            }
+        }
+        if (wc) {
+            const int my = a.H - oy0 < RT ? a.H - oy0 : RT, mx = a.W - ox0 < RT ? a.W - ox0 : RT;
+            work += 2ull * 2ull * my * mx * 32ull * 288ull;   // both convolutions, valid outputs only
+        }
+        __syncthreads();
+        if (tn >= ntiles) break;
+        t = tn;
+    }
+    if (wc && tid == 0) work_atomic(wc, work);
+}
+
+int launch_resblock32(const ResArgs& a, hipStream_t s) {
+    if (a.B <= 0 || a.H <= 0 || a.W <= 0) return HELM_OK;
+    if (a.K1 < 288 || a.K2 < 288) return fail(HELM_EINVAL, "resblock32: weight depth below 9 x 32");
+    if ((long)a.B * a.H * a.W >= (1L << 31) / 32) return fail(HELM_EINVAL, "resblock32: grid too large");
+    static int res = 0;
+    const int tiles = ((a.H + RT - 1) / RT) * ((a.W + RT - 1) / RT) * a.B;
+    const int gx = std::max(1, std::min(tiles, resident_blocks(k_resblock32, res)));
+    TIMED_LAUNCH("k_conv", s, k_resblock32, dim3(gx), dim3(256), 0, s, a, WORK_COUNTER("k_conv", s));
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
+}
+
+// The halo kernels apply when every source has a multiple of 32 channels.
+static bool halo_ok(const GemmArgs& a) {
+    if (!(a.gmode == G_CONV || a.gmode == G_CONVT) || a.stride != 1) return false;
+    if (a.c1 % HC || a.c2 % HC) return false;
+    if (a.gmode == G_CONV && a.epi != E_FWD) return false;
+    if (a.gmode == G_CONVT && a.epi != E_ACC) return false;
+    return a.K >= 9 * (a.c1 + a.c2);
+}
+
 
 template <int BN, int FLIP, int EPI, int NCH>
 static void launch_pers(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {

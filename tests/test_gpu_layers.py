@@ -105,3 +105,18 @@ def test_autotuner_choice_keeps_results(gpu):
     n1 = api.helm_autotune(-1)
     assert n0 == 0 and n1 >= 1
     assert relerr(y0, ref) <= 1e-5 and relerr(y1, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("B,H,W_", [(2, 14, 14), (2, 37, 50), (1, 16, 30), (3, 5, 9)])
+def test_fused_resblock32(gpu, B, H, W_):
+    """y = x + conv2(ReLU(conv1(x) + b1)) + b2 in one kernel (14 x 14 output
+    tiles): against the oracle's layers, ragged tiles and grids smaller than a tile."""
+    x = rnd((B, H, W_, 32), 21)
+    W1 = rnd((32, 3, 3, 32), 22, scale=np.sqrt(2.0 / 288))
+    W2 = rnd((32, 3, 3, 32), 23, scale=np.sqrt(2.0 / 288))
+    b1 = rnd((32,), 24, 0.1)
+    b2 = rnd((32,), 25, 0.1)
+    y = api.cnn_layer_resblock(x, W1, b1, W2, b2)
+    h = bf(np.maximum(U.conv3x3(x, W1, b1, 1), 0))       # the kernel keeps h in BF16
+    ref = x + U.conv3x3(h, W2, b2, 1)
+    assert relerr(y, ref) <= 5e-3                         # output stored in BF16
