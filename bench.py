@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--precond", default="cnn_vu", choices=["mg", "cnn_vu", "cnn"])
-    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--restart", type=int, default=10, help="FGMRES cycle length of the CNN preconditioners")
     ap.add_argument("--maxit", type=int, default=2000)
@@ -131,7 +131,7 @@ def cpu_baseline(med, src, nrhs):
                       f"{dt:.1f} s, iterations {its}"}
 
 
-def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=1000):
+def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=500):
     """Adam on fresh eq. (4.3) pairs in rounds of 500 steps (lr0 for 1000 steps,
     lr0/2 up to 3000, lr0/4 after).  Every eval_every steps the network is
     scored by the mean CNN-FGMRES iteration count on 8 validation sources (row

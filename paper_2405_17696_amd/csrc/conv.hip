@@ -689,6 +689,80 @@ __global__ __launch_bounds__(256) void k_conv3_smallc(GemmArgs a, unsigned long 
     }
 }
 
+// Two-channel first layer on the matrix cores: K = 9 taps x 2 channels = 18,
+// padded to one 32-deep MFMA step.  Lane l gathers, for pixel l%16 of a
+// 16-pixel row segment, the 8 (tap, channel) values k = 8(l/16) .. +7 with
+// 4-byte loads; the weight fragments stay in registers for the whole launch.
+// Waves walk over row segments with a grid stride.
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3_first2(GemmArgs a, unsigned long long* wc) {
+    const int lane = threadIdx.x & 63;
+    const long wave0 = ((long)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const long nwaves = (long)gridDim.x * 4;
+    const int segs_x = (a.Wo + 15) / 16;
+    const long nseg = (long)a.B * a.Ho * segs_x;
+    const int kg = lane >> 4;                  // k = 8 kg .. 8 kg + 7
+    bf16x8 fw[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) fw[j] = ld8(a.w + (long)(j * 16 + (lane & 15)) * a.K + kg * 8);
+    float bias[NT][4];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[j][e] = a.bias[j * 16 + kg * 4 + e];
+    unsigned long long work = 0;
+    for (long sgi = wave0; sgi < nseg; sgi += nwaves) {
+        const int sx = (int)(sgi % segs_x);
+        const long rowi = sgi / segs_x;
+        const int y = (int)(rowi % a.Ho), b = (int)(rowi / a.Ho);
+        if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) continue;
+        const int x = sx * 16 + (lane & 15);
+        // gather taps 4 kg .. 4 kg + 3 (two channels each); taps >= 9 are the zero padding
+        bf16x8 fx = zero8();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int tap = kg * 4 + q;
+            if (tap >= 9) break;
+            const int yi = y + tap / 3 - 1, xi = x + tap % 3 - 1;
+            if (x < a.Wo && yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi) {
+                const bf16* src = a.a1 + b * a.abs1 + ((long)yi * a.Wi + xi) * 2;
+                fx[2 * q] = src[0];
+                fx[2 * q + 1] = src[1];
+            }
+        }
+        if (x < a.Wo) work += 2ull * 18 * a.N;
+        const long m = ((long)b * a.Ho + y) * a.Wo + x;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fx, (f32x4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            if (x >= a.Wo) continue;
+            const int n = j * 16 + kg * 4;
+            bf16x4g o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = acc[e] + bias[j][e];
+                if (a.resid) v += (float)a.resid[m * a.N + n + e];
+                if (a.relu) v = v > 0.f ? v : 0.f;
+                o[e] = (bf16)v;
+                acc[e] = v;
+            }
+            if (a.out) *reinterpret_cast<bf16x4g*>(a.out + m * a.N + n) = o;
+            if (a.outf) *reinterpret_cast<f32x4*>(a.outf + m * a.N + n) = acc;
+        }
+    }
+    if (wc) {
+        // one counter update per wave
+        unsigned long long tot = work;
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+        if (lane == 0) work_atomic(wc, tot);
+    }
+}
+
+static bool first2_ok(const GemmArgs& a) {
+    return a.gmode == G_CONV && a.stride == 1 && a.epi == E_FWD && !a.bmap && a.c2 == 0 && a.c1 == 2 &&
+           a.N % 16 == 0 && a.N <= 64 && a.K >= 32;
+}
+
 static bool smallc_ok(const GemmArgs& a) {
     return a.gmode == G_CONV && a.stride == 1 && a.epi == E_FWD && !a.bmap && a.c2 == 0 && a.c1 >= 1 && a.c1 <= 4 &&
            a.N % 8 == 0 && a.N <= SC_MAXN && a.K >= 9 * a.c1;
@@ -905,7 +979,7 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // (outside stream capture) times every applicable candidate on the caller's
 // buffers and keeps the fastest for that shape.  Only overwriting epilogues are
 // tuned (accumulating ones would add each candidate's result).
-enum ConvKernel { CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_COUNT };
+enum ConvKernel { CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_COUNT };
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
     const bool halo = halo_ok(a);
@@ -917,6 +991,7 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_GEMM64:
         case CK_GEMM128: return true;
         case CK_SMALLC: return smallc_ok(a);
+        case CK_FIRST2: return first2_ok(a);
     }
     return false;
 }
@@ -926,6 +1001,7 @@ static int ck_default(const GemmArgs& a) {
         if (ck_applicable(a, CK_PERS)) return CK_PERS;
         return a.N <= 32 ? CK_HALO32 : CK_HALO64;
     }
+    if (first2_ok(a)) return CK_FIRST2;
     if (smallc_ok(a)) return CK_SMALLC;
     return a.N <= 32 ? CK_GEMM128 : CK_GEMM64;
 }
@@ -955,6 +1031,17 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
             else
                 launch_halo_ck<0, E_FWD>(a, s, wc, ck);
             break;
+        case CK_FIRST2: {
+            const long nseg = (long)a.B * a.Ho * ((a.Wo + 15) / 16);
+            const dim3 grid((unsigned)std::max<long>(1, std::min<long>(4096, (nseg + 3) / 4)));
+            switch (a.N / 16) {
+                case 1: TIMED_LAUNCH("k_conv", s, k_conv3_first2<1>, grid, dim3(256), 0, s, a, wc); break;
+                case 2: TIMED_LAUNCH("k_conv", s, k_conv3_first2<2>, grid, dim3(256), 0, s, a, wc); break;
+                case 3: TIMED_LAUNCH("k_conv", s, k_conv3_first2<3>, grid, dim3(256), 0, s, a, wc); break;
+                default: TIMED_LAUNCH("k_conv", s, k_conv3_first2<4>, grid, dim3(256), 0, s, a, wc); break;
+            }
+            break;
+        }
         case CK_SMALLC: {
             const dim3 grid((unsigned)std::min<long>(2048, (a.M * (a.N / 8) + 255) / 256));
             switch (a.c1) {

@@ -27,6 +27,8 @@ CONV_CASES = [
     ("concat", 1, 2, 8, 8, 32, 32, False, 32, True, False),
     ("bcast", 1, 3, 8, 8, 64, 64, True, 64, True, False),
     ("first", 1, 2, 16, 16, 2, 0, False, 32, True, False),
+    ("first_n48", 1, 2, 12, 20, 2, 0, False, 48, True, False),   # matrix-core first layer, three channel tiles
+    ("first_c3", 1, 2, 16, 16, 3, 0, False, 32, True, False),    # FP32 first-layer kernel
     ("last", 1, 2, 8, 8, 32, 0, False, 2, False, False),
     ("resid", 1, 2, 8, 8, 32, 0, False, 32, False, True),
     ("wide", 2, 1, 8, 8, 128, 0, False, 256, True, False),
