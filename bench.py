@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
+    ap.add_argument("--tune-file", default=None,
+                    help="load convolution kernel choices from this file if it exists, save them after the run")
     return ap.parse_args()
 
 
@@ -408,7 +410,13 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if a.tune_file and os.path.exists(a.tune_file):
+        from paper_2405_17696_amd import api
+        api.helm_autotune_file(a.tune_file, save=False)
     {"c2": main_c2, "c3": main_c3, "c4": main_c4, "c5": main_c5}[a.workload](a)
+    if a.tune_file:
+        from paper_2405_17696_amd import api
+        api.helm_autotune_file(a.tune_file, save=True)
 
 
 if __name__ == "__main__":

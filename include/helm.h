@@ -249,6 +249,10 @@ int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsr
  * shapes tuned so far.
  */
 int helm_autotune(int enable, int* tuned_shapes);
+/* Tuned kernel choices to (save = 1) or from (save = 0, merged into the current
+ * table) a text file (host path), so that another process launches exactly the
+ * same kernels for the same shapes. */
+int helm_autotune_file(const char* path, int save);
 
 /*
  * Diagnostics: time every launch of one named kernel ("k_matvec_dot",

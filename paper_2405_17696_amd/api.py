@@ -144,6 +144,11 @@ def helm_autotune(enable: int = -1) -> int:
     return n.value
 
 
+def helm_autotune_file(path, save: bool):
+    """Save the tuned convolution kernel choices to, or merge them from, a text file."""
+    L.check(L.load().helm_autotune_file(str(path).encode(), int(save)))
+
+
 # ---------------------------------------------------------------- encoder-solver network
 class CnnNet:
     """Owning wrapper of a cnn_net_t handle."""

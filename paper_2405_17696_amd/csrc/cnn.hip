@@ -1778,3 +1778,8 @@ extern "C" int helm_autotune(int enable, int* tuned_shapes) {
     if (enable < -1 || enable > 2) return fail(HELM_EINVAL, "helm_autotune: enable must be -1, 0, 1 or 2");
     return conv_autotune(enable, tuned_shapes);
 }
+
+extern "C" int helm_autotune_file(const char* path, int save) {
+    if (!path) return fail(HELM_EINVAL, "helm_autotune_file: path is NULL");
+    return conv_autotune_file(path, save);
+}

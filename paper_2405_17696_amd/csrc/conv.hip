@@ -1160,6 +1160,38 @@ int launch_gemm(const GemmArgs& a, hipStream_t s) {
     return launch_ck(a, s, ck, WORK_COUNTER("k_conv", s));
 }
 
+// Tuned choices to / from a text file (one shape per line: 16 key fields, then
+// the kernel), so that another process can launch exactly the same kernels.
+int conv_autotune_file(const char* path, int save) {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    if (save) {
+        FILE* f = fopen(path, "w");
+        if (!f) return fail(HELM_EINVAL, "helm_autotune_file: cannot write %s", path);
+        for (const auto& kv : g_tuned) {
+            for (int i = 0; i < 16; ++i) fprintf(f, "%d ", kv.first.v[i]);
+            fprintf(f, "%d\n", kv.second);
+        }
+        fclose(f);
+        return HELM_OK;
+    }
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(HELM_EINVAL, "helm_autotune_file: cannot read %s", path);
+    for (;;) {
+        TuneKey k{};
+        int ck = 0, got = 0;
+        for (int i = 0; i < 16; ++i) got += fscanf(f, "%d", &k.v[i]);
+        got += fscanf(f, "%d", &ck);
+        if (got != 17) break;
+        if (ck < 0 || ck >= CK_COUNT) {
+            fclose(f);
+            return fail(HELM_EINVAL, "helm_autotune_file: bad kernel id %d in %s", ck, path);
+        }
+        g_tuned[k] = ck;
+    }
+    fclose(f);
+    return HELM_OK;
+}
+
 int conv_autotune(int enable, int* tuned) {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     if (enable == 0 || enable == 1) g_tune_on = enable == 1;

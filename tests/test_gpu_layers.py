@@ -92,7 +92,7 @@ def test_upconv_layer_forward_backward(gpu, B, H, W_, cin, cout):
     assert relerr(gb, rb) <= 1e-5
 
 
-def test_autotuner_choice_keeps_results(gpu):
+def test_autotuner_choice_keeps_results(gpu, tmp_path):
     """Tuned and rule-based kernel choices give the same layer within BF16 rounding."""
     x1 = rnd((2, 40, 48, 32), 11)
     Wt = rnd((32, 3, 3, 32), 12, scale=np.sqrt(2.0 / 288))
@@ -107,6 +107,15 @@ def test_autotuner_choice_keeps_results(gpu):
     n1 = api.helm_autotune(-1)
     assert n0 == 0 and n1 >= 1
     assert relerr(y0, ref) <= 1e-5 and relerr(y1, ref) <= 1e-5
+    # the tuned table survives a save / clear / load round trip
+    f = tmp_path / "tune.txt"
+    api.helm_autotune_file(f, save=True)
+    api.helm_autotune(2)
+    assert api.helm_autotune(-1) == 0
+    api.helm_autotune_file(f, save=False)
+    assert api.helm_autotune(-1) == n1
+    y2 = api.cnn_layer_forward(0, 1, x1, Wt, b, relu=True)
+    assert np.array_equal(y1, y2)
 
 
 @pytest.mark.parametrize("B,H,W_", [(2, 14, 14), (2, 37, 50), (1, 16, 30), (3, 5, 9)])
