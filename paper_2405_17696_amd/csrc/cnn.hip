@@ -502,7 +502,7 @@ struct Program {
 struct EncCtx {
     uint64_t net_uid = 0, ver = 0;
     Tens zt[4];              // batch-1 views of z_l
-    float* zc[4] = {nullptr, nullptr, nullptr, nullptr};
+    bf16* zc[4] = {nullptr, nullptr, nullptr, nullptr};   // z parts of the context convolutions (+ bias)
     std::vector<void*> allocs;
     ~EncCtx() {
         for (void* p : allocs) (void)hipFree(p);
@@ -949,8 +949,7 @@ static int encode(cnn_net* net, const helm_op* op, Arena& A, hipStream_t s, EncC
         g.epi = E_FWD;
         g.bias = net->master + L.boff;
         g.relu = 0;
-        g.out = nullptr;
-        g.outf = ctx->zc[l];
+        g.out = ctx->zc[l];
         g.M = (long)z.H * z.W;
         if ((rc = launch_gemm(g, s))) return rc;
     }
@@ -979,12 +978,12 @@ static int ensure_encoded(cnn_net* net, const helm_op* op, Arena* A, hipStream_t
             ctx->allocs.push_back(p);
             t.d = (bf16*)p;
             ctx->zt[l] = t;
-            if (hipMalloc(&p, sizeof(float) * t.n()) != hipSuccess) {
+            if (hipMalloc(&p, sizeof(bf16) * t.n()) != hipSuccess) {
                 delete ctx;
                 return fail(HELM_ENOMEM, "cnn: encoder context");
             }
             ctx->allocs.push_back(p);
-            ctx->zc[l] = (float*)p;
+            ctx->zc[l] = (bf16*)p;
         }
         const_cast<helm_op*>(op)->enc.ctx = ctx;
     }

@@ -49,7 +49,7 @@ struct GemmArgs {
     long M;
     const RhsState* st;  // optional: skip row tiles of samples whose RHS is inactive
     int rhs0;
-    const float* bmap;   // E_FWD: fp32 [Ho][Wo][N] added instead of bias (same for every sample)
+    const bf16* bmap;    // E_FWD: [Ho][Wo][N] added instead of bias (same for every sample)
 };
 
 struct WgradArgs {

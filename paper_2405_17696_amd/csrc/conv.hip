@@ -26,6 +26,13 @@ __device__ __forceinline__ bf16x8 zero8() {
 
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
+// Four consecutive BF16 values of a per-pixel bias map, widened.
+__device__ __forceinline__ float4 bmap4(const bf16* p) {
+    typedef __bf16 bf16x4m __attribute__((ext_vector_type(4)));
+    const bf16x4m v = *reinterpret_cast<const bf16x4m*>(p);
+    return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+
 // Pixel (b, y, x) of row m of a B x Ho x Wo grid.
 struct Pix {
     int b, y, x;
@@ -218,8 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
             if (a.epi == E_FWD) {
                 const long pm = m % ((long)a.Ho * a.Wo);     // pixel within the sample (bmap index)
                 if ((a.N & 3) == 0) {
-                    const float4 bb = a.bmap ? *reinterpret_cast<const float4*>(a.bmap + pm * a.N + n)
-                                             : *reinterpret_cast<const float4*>(a.bias + n);
+                    const float4 bb = a.bmap ? bmap4(a.bmap + pm * a.N + n) : *reinterpret_cast<const float4*>(a.bias + n);
                     v[0] += bb.x;
                     v[1] += bb.y;
                     v[2] += bb.z;
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (n + e >= a.N) break;
-                        float w = v[e] + (a.bmap ? a.bmap[pm * a.N + n + e] : a.bias[n + e]);
+                        float w = v[e] + (a.bmap ? (float)a.bmap[pm * a.N + n + e] : a.bias[n + e]);
                         if (a.resid) w += (float)a.resid[m * a.N + n + e];
                         if (a.relu) w = w > 0.f ? w : 0.f;
                         if (a.out) a.out[m * a.N + n + e] = (bf16)w;
@@ -448,7 +454,7 @@ __device__ __forceinline__ void halo_epilogue(const GemmArgs& a, const f32x4 (&a
             f32x4 v = acc[i][j];
             if (EPI == E_FWD) {
                 if (vec) {
-                    const float4 bb = a.bmap ? *reinterpret_cast<const float4*>(a.bmap + ((long)y * a.Wo + x) * a.N + n)
+                    const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
                                              : *reinterpret_cast<const float4*>(a.bias + n);
                     v[0] += bb.x;
                     v[1] += bb.y;
@@ -473,7 +479,7 @@ __device__ __forceinline__ void halo_epilogue(const GemmArgs& a, const f32x4 (&a
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (n + e >= a.N) break;
-                        float w = v[e] + (a.bmap ? a.bmap[((long)y * a.Wo + x) * a.N + n + e] : a.bias[n + e]);
+                        float w = v[e] + (a.bmap ? (float)a.bmap[((long)y * a.Wo + x) * a.N + n + e] : a.bias[n + e]);
                         if (a.resid) w += (float)a.resid[m * a.N + n + e];
                         if (a.relu) w = w > 0.f ? w : 0.f;
                         if (a.out) a.out[m * a.N + n + e] = (bf16)w;
