@@ -1,0 +1,71 @@
+"""The measured workloads at their full sizes, checked on sampled outputs the
+oracle can compute one by one and on properties that hold at any size.
+
+* 256 x 256 layered medium, 32 surface sources, one batched launch (the bench
+  workload): CNN-FGMRES(10) with M_VU and MG-GMRES(20); every returned solution's
+  FP64 residual is recomputed by the oracle's operator, and sampled right-hand
+  sides are compared with the oracle's sparse direct solve.
+* 512 x 512 FWI setting (four frequencies, 128 receivers on row 4): the misfit
+  gradient against the oracle's adjoint-state gradient, with two of the 128
+  sources (the oracle factorises each frequency once).
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import f32, relerr
+from oracle import fwi
+from oracle import operator as op
+from paper_2405_17696_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2(gpu):
+    med, src = synth.config2_medium()
+    med.kappa2 = f32(med.kappa2)
+    med.gamma = f32(med.gamma)
+    H = api.helm_setup(torch.tensor(med.kappa2, dtype=torch.float32, device="cuda"),
+                       torch.tensor(med.gamma, dtype=torch.float32, device="cuda"), med.omega, med.h)
+    coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
+    return med, src, H, coef
+
+
+@pytest.mark.parametrize("precond,restart", [("cnn_vu", 10), ("mg", 20)])
+def test_bench_workload_full_size(c2, precond, restart):
+    med, src, H, coef = c2
+    print("full-size c2", precond, flush=True)
+    net = api.cnn_create(seed=1) if precond != "mg" else None
+    b = torch.tensor(src, dtype=torch.complex64, device="cuda")
+    x, it, rr, st, code = api.helm_solve(H, b, tol=1e-6, precond=precond, maxit=3000, net=net, restart=restart,
+                                         use_graph=True)
+    assert code == 0 and np.all(st == 0)
+    xh = x.cpu().numpy()
+    rel = op.relres(coef, xh, src.astype(np.complex128), med.h, med.h)
+    assert np.all(rel <= 1e-6)
+    assert np.allclose(rel, rr, rtol=1e-3, atol=1e-12)
+    S = op.DirectSolver(op.assemble(coef, med.h, med.h))
+    for r in (0, 17, 31):
+        xs = S.solve(src[r].astype(np.complex128).ravel())
+        assert relerr(xh[r].ravel(), xs) <= 1e-4
+
+
+def test_fwi_gradient_full_grid(gpu):
+    d = synth.config5_media(nsrc=128, nrec=128)
+    k2 = f32(d["kappa2_init"])
+    kt = f32(d["kappa2_true"])
+    gam = f32(d["gamma"])
+    src = np.asarray(d["src_idx"])[[20, 90]]
+    rec = np.asarray(d["rec_idx"])
+    h, omegas = d["h"], d["omegas"]
+    print("full-grid fwi gradient", flush=True)
+    dobs = fwi.forward_data(kt, gam, omegas, h, src, rec).astype(np.complex64).astype(np.complex128)
+    phi_o, g_o = fwi.misfit_and_grad(k2, gam, omegas, h, src, rec, dobs)
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    ops = [api.helm_setup(t(k2), t(gam), w, h) for w in omegas]
+    phi, g, its, code = api.fwi_misfit_grad(ops, src, rec, torch.tensor(dobs, dtype=torch.complex64, device="cuda"),
+                                            tol=1e-6, precond="mg", maxit=3000, restart=20)
+    assert code == 0
+    assert abs(phi - phi_o) <= 1e-2 * phi_o
+    assert relerr(g.cpu().numpy().astype(np.float64), g_o) <= 1e-3
