@@ -327,39 +327,80 @@ constexpr int HC = 32;              // channels per chunk
 constexpr int HLD = HC + 8;         // padded LDS row (bf16)
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+// 16-byte raw buffer load; an offset at or past the descriptor's byte count reads zeros.
+__device__ __forceinline__ bf16x8 bload8(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return __builtin_bit_cast(bf16x8, v);
+}
+// Raw buffer descriptor over nbytes at p (dword data format, no stride).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* p, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+
+// Register staging of one 32-channel chunk of a tile's patch (and of the nine
+// taps of BN output channels' weights).  The per-thread byte offsets of its
+// segments are computed once per tile (and input half) and once per block for
+// the weights; a chunk's loads then only add the channel offset.  Patch pixels
+// outside the image and weight rows past N get an offset past the end of their
+// buffer, so the buffer loads return zeros without a branch.
 template <int BN>
 struct HaloStage {
     static constexpr int PSEG = HP * HP * (HC / 8);   // 16-byte segments of the patch
     static constexpr int WSEG = 9 * BN * (HC / 8);    // and of the weights
     static constexpr int PPT = (PSEG + 255) / 256, WPT = (WSEG + 255) / 256;
     bf16x8 rp[PPT], rw[WPT];
+    unsigned po[PPT], wo[WPT];
+    __amdgpu_buffer_rsrc_t rs_p, rs_w;
+    int half = -1;   // input half the patch offsets refer to (0: a1, 1: a2)
 
-    __device__ __forceinline__ void load(const GemmArgs& a, int tid, int b, int ty0, int tx0, int n0, int c0,
-                                         bool weights) {
-        const bool s2 = c0 >= a.c1;
+    // Patch offsets of the 16 x 16 tile at (ty0, tx0) of sample b in input half s2.
+    __device__ __forceinline__ void tile(const GemmArgs& a, int tid, int b, int ty0, int tx0, int s2) {
         const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
-        const int cs = s2 ? a.c2 : a.c1, cc = s2 ? c0 - a.c1 : c0;
-        const int C = a.c1 + a.c2;
+        const int cs = s2 ? a.c2 : a.c1;
+        const unsigned nrec = (unsigned)a.Hi * (unsigned)a.Wi * (unsigned)cs * 2u;
+        rs_p = brsrc(src, nrec);
+        half = s2;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int sg = tid + q * 256;
-            if (sg >= PSEG) break;
             const int pix = sg >> 2, sub = sg & 3;
             const int py = pix / HP, px = pix - py * HP;
             const int yi = ty0 + py - 1, xi = tx0 + px - 1;
-            rp[q] = (yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi)
-                        ? ld8(src + ((long)yi * a.Wi + xi) * cs + cc + sub * 8)
-                        : zero8();
+            const bool in = sg < PSEG && (unsigned)yi < (unsigned)a.Hi && (unsigned)xi < (unsigned)a.Wi;
+            po[q] = in ? ((unsigned)(yi * a.Wi + xi) * (unsigned)cs + (unsigned)(sub * 8)) * 2u : nrec;
         }
-        if (!weights) return;
+    }
+    // Weight offsets of output channels n0 .. n0 + BN - 1 (rows [N][K], K = 9 C tap-major).
+    __device__ __forceinline__ void wset(const GemmArgs& a, int tid, int n0) {
+        const unsigned nrec = (unsigned)a.N * (unsigned)a.K * 2u;
+        rs_w = brsrc(a.w, nrec);
+        const int C = a.c1 + a.c2;
 #pragma unroll
         for (int q = 0; q < WPT; ++q) {
             const int sg = tid + q * 256;
-            if (sg >= WSEG) break;
             const int row = sg >> 2, sub = sg & 3;   // row = tap * BN + n
             const int tap = row / BN, n = row - tap * BN;
-            rw[q] = n0 + n < a.N ? ld8(a.w + (long)(n0 + n) * a.K + tap * C + c0 + sub * 8) : zero8();
+            wo[q] = sg < WSEG && n0 + n < a.N ? (unsigned)((n0 + n) * a.K + tap * C + sub * 8) * 2u : nrec;
         }
+    }
+    // Chunk at absolute input channel c0 (the patch offsets must refer to its half).
+    __device__ __forceinline__ void issue(const GemmArgs& a, int tid, int c0, bool weights) {
+        const unsigned cc = (unsigned)(half ? c0 - a.c1 : c0) * 2u;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            if (tid + q * 256 < PSEG) rp[q] = bload8(rs_p, po[q] + cc);
+        if (!weights) return;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q)
+            if (tid + q * 256 < WSEG) rw[q] = bload8(rs_w, wo[q] + (unsigned)c0 * 2u);
+    }
+    // All in one: offsets for this tile (and weights), then the loads.
+    __device__ __forceinline__ void load(const GemmArgs& a, int tid, int b, int ty0, int tx0, int n0, int c0,
+                                         bool weights) {
+        tile(a, tid, b, ty0, tx0, c0 >= a.c1);
+        if (weights) wset(a, tid, n0);
+        issue(a, tid, c0, weights);
     }
     template <int WLD>
     __device__ __forceinline__ void store(bf16 (*Ps)[HLD], bf16 (*Ws)[BN][WLD], int tid, bool weights) const {
@@ -510,6 +551,69 @@ __device__ __forceinline__ void halo_epilogue(const GemmArgs& a, const f32x4 (&a
     }
 }
 
+// Forward epilogue through LDS: each lane finishes its accumulators as above
+// (bias or bias map, residual, ReLU, one rounding to bf16) but writes them to an
+// LDS copy of the block's 16 x 16 x BN output tile; after a barrier every lane
+// stores 16 contiguous bytes, so a pixel's BN channels leave as whole 64- or
+// 128-byte lines in one instruction instead of four 8-byte pieces per lane
+// spread over 16 pixels (partial-line writes ran at under 2 TB/s).  scratch
+// holds 256 (BN + 8) bf16; every thread of the block must call this.
+template <int BN>
+__device__ __forceinline__ bool halo_lds_epilogue_ok(const GemmArgs& a) {
+    return a.out && !a.outf && (a.N & 7) == 0;
+}
+template <int BN>
+__device__ __forceinline__ void halo_epilogue_lds(const GemmArgs& a, const f32x4 (&acc)[4][BN / 16], int b, int ty0,
+                                                  int tx0, int n0, int tid, bf16* scratch) {
+    constexpr int WTN = BN / 16, SP = BN + 8;   // LDS pixel stride (bf16), 16-byte aligned rows
+    const int lane = tid & 63, wave = tid >> 6;
+    const int x = tx0 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ty0 + wave * 4 + i;
+        const bool in = x < a.Wo && y < a.Ho;
+        const long m = ((long)b * a.Ho + y) * a.Wo + x;
+        const int p = (wave * 4 + i) * HT + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            const int nl = j * 16 + (lane >> 4) * 4, n = n0 + nl;
+            f32x4 v = acc[i][j];
+            if (in && n < a.N) {
+                const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
+                                         : *reinterpret_cast<const float4*>(a.bias + n);
+                v[0] += bb.x;
+                v[1] += bb.y;
+                v[2] += bb.z;
+                v[3] += bb.w;
+                if (a.resid) {
+                    const bf16x4 r = *reinterpret_cast<const bf16x4*>(a.resid + m * a.N + n);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
+                }
+                if (a.relu)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+            }
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+            *reinterpret_cast<bf16x4*>(scratch + p * SP + nl) = o;
+        }
+    }
+    __syncthreads();
+    constexpr int CPP = BN / 8;                   // 16-byte chunks per pixel
+#pragma unroll
+    for (int r = 0; r < CPP; ++r) {
+        const int k = tid + r * 256;
+        const int p = k / CPP, c = k - p * CPP;
+        const int y = ty0 + p / HT, xx = tx0 + (p & (HT - 1)), n = n0 + c * 8;
+        if (y < a.Ho && xx < a.Wo && n < a.N)
+            *reinterpret_cast<bf16x8*>(a.out + (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n) =
+                *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ unsigned long long halo_work(const GemmArgs& a, int ty0, int tx0, int n0, int bn) {
     const int my = a.Ho - ty0 < HT ? a.Ho - ty0 : HT, mx = a.Wo - tx0 < HT ? a.Wo - tx0 : HT;
     const int nr = a.N - n0 < bn ? a.N - n0 : bn;
@@ -523,10 +627,10 @@ __device__ __forceinline__ void halo_count(const GemmArgs& a, unsigned long long
 // One tile per block; the next chunk's patch and weights are prefetched into
 // registers while the current chunk runs.
 template <int BN, int FLIP, int EPI>
-__global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long long* wc) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN <= 32 ? 3 : 2))) void k_conv3_halo(GemmArgs a, unsigned long long* wc) {
     constexpr int WTN = BN / 16;
-    __shared__ bf16 Ps[HP * HP][HLD];
-    __shared__ bf16 Ws[9][BN][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ps[HP * HP][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[9][BN][HLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (a.Wo + HT - 1) / HT, tiles_y = (a.Ho + HT - 1) / HT;
     int t = blockIdx.x;
@@ -548,11 +652,19 @@ __global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long lo
     for (int ch = 0; ch < nchunk; ++ch) {
         st.store(Ps, Ws, tid, true);
         __syncthreads();
-        if (ch + 1 < nchunk) st.load(a, tid, b, ty0, tx0, n0, (ch + 1) * HC, true);
+        if (ch + 1 < nchunk) {
+            const int c0 = (ch + 1) * HC;
+            if (c0 == a.c1) st.tile(a, tid, b, ty0, tx0, 1);
+            st.issue(a, tid, c0, true);
+        }
         halo_mma<BN, FLIP>(Ps, Ws, 0, acc, lane, wave);
         __syncthreads();
     }
-    halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
+    static_assert(sizeof(Ws) >= 256 * (BN + 8) * sizeof(bf16), "epilogue scratch");
+    if (EPI == E_FWD && halo_lds_epilogue_ok<BN>(a))
+        halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ws[0][0][0]);
+    else
+        halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 }
 
 // Persistent form for layers of NCH * 32 input channels (NCH = 1, 2) and at most
@@ -560,11 +672,11 @@ __global__ __launch_bounds__(256) void k_conv3_halo(GemmArgs a, unsigned long lo
 // (tile, chunk) items with a stride of gridDim.x tiles, and prefetches the next
 // item's patch into registers while the current one runs.
 template <int BN, int FLIP, int EPI, int NCH>
-__global__ __launch_bounds__(256) void k_conv3_pers(GemmArgs a, unsigned long long* wc) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 1 ? 3 : 2))) void k_conv3_pers(GemmArgs a, unsigned long long* wc) {
     constexpr int WTN = BN / 16;
     constexpr int WLD = NCH * HC + 8;
-    __shared__ bf16 Ps[HP * HP][HLD];
-    __shared__ bf16 Ws[9][BN][WLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ps[HP * HP][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[9][BN][WLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (a.Wo + HT - 1) / HT, tiles_y = (a.Ho + HT - 1) / HT;
     const int tps = tiles_x * tiles_y;
@@ -609,7 +721,11 @@ __global__ __launch_bounds__(256) void k_conv3_pers(GemmArgs a, unsigned long lo
         if (ch == NCH - 1) {
             const int b = t / tps, ty0 = ((t / tiles_x) % tiles_y) * HT, tx0 = (t % tiles_x) * HT;
             work += halo_work(a, ty0, tx0, n0, BN);
-            halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
+            constexpr bool fits = sizeof(Ps) >= 256 * (BN + 8) * sizeof(bf16);
+            if (EPI == E_FWD && fits && halo_lds_epilogue_ok<BN>(a))
+                halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ps[0][0]);
+            else
+                halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -799,9 +915,9 @@ static int resident_blocks(K kernel, int& cache) {
 constexpr int RT = HT - 2;   // output tile edge (14)
 
 __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long long* wc) {
-    __shared__ bf16 Ps[HP * HP][HLD];
-    __shared__ bf16 W1s[9][32][HLD];
-    __shared__ bf16 W2s[9][32][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ps[HP * HP][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 W1s[9][32][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 W2s[9][32][HLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (a.W + RT - 1) / RT, tiles_y = (a.H + RT - 1) / RT, tps = tiles_x * tiles_y;
     const int ntiles = a.B * tps;
@@ -900,20 +1016,31 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
         halo_mma<32, 0>(Ps, W2s, 0, acc, lane, wave);
+        // the RT x RT outputs go through the patch buffer so that every pixel's 64 bytes
+        // leave in one store instruction (16 contiguous bytes per lane)
+        __syncthreads();
+        bf16* ob = &Ps[0][0];
+        constexpr int OSP = 40;   // bf16 per output pixel in LDS
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int py = wave * 4 + i;
-            const int y = oy0 - 1 + py, x = ox0 - 1 + px;
-            if (py < 1 || py > RT || px < 1 || px > RT || y >= a.H || x >= a.W) continue;
-            const long m = ((long)b * a.H + y) * a.W + x;
+            if (py < 1 || py > RT || px < 1 || px > RT) continue;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int n = j * 16 + (lane >> 4) * 4;
                 bf16x4r o;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) o[e] = (bf16)(acc[i][j][e] + a.b2[n + e] + (float)res[i][j][e]);
-                *reinterpret_cast<bf16x4r*>(a.out + m * 32 + n) = o;
+                *reinterpret_cast<bf16x4r*>(ob + ((py - 1) * RT + px - 1) * OSP + n) = o;
             }
+        }
+        __syncthreads();
+        for (int k = tid; k < RT * RT * 4; k += 256) {
+            const int p = k >> 2, c = k & 3;
+            const int y = oy0 + p / RT, x = ox0 + p % RT;
+            if (y < a.H && x < a.W)
+                *reinterpret_cast<bf16x8*>(a.out + (((long)b * a.H + y) * a.W + x) * 32 + c * 8) =
+                    *reinterpret_cast<const bf16x8*>(ob + p * OSP + c * 8);
         }
         if (wc) {
             const int my = a.H - oy0 < RT ? a.H - oy0 : RT, mx = a.W - ox0 < RT ? a.W - ox0 : RT;
@@ -944,6 +1071,9 @@ static bool halo_ok(const GemmArgs& a) {
     if (a.c1 % HC || a.c2 % HC) return false;
     if (a.gmode == G_CONV && a.epi != E_FWD) return false;
     if (a.gmode == G_CONVT && a.epi != E_ACC) return false;
+    // the staging addresses one sample's input half and the weights with 32-bit byte offsets
+    if ((long)a.Hi * a.Wi * std::max(a.c1, a.c2) * 2 + 4096 >= (1L << 31)) return false;
+    if ((long)a.N * a.K * 2 >= (1L << 31)) return false;
     return a.K >= 9 * (a.c1 + a.c2);
 }
 
