@@ -129,8 +129,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
     constexpr int BSEG = BN * KC / 8;
     constexpr int AS_PER_T = (ASEG + 255) / 256;
     constexpr int BS_PER_T = (BSEG + 255) / 256;
-    __shared__ bf16 As[2][BM][LDS_K];
-    __shared__ bf16 Bs[2][BN][LDS_K];
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM][LDS_K];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN][LDS_K];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const long m0 = (long)blockIdx.x * BM;
@@ -212,7 +212,77 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
 
     // epilogue: the MFMA ran with the weights as A, so acc[i][j][e] holds
     // D[m = row tile i + l%16][n = column tile j + 4 (l/16) + e]: four consecutive
-    // output channels of one pixel per lane
+    // output channels of one pixel per lane.
+    // Overwriting bf16 outputs go through LDS: each lane finishes and rounds its
+    // four values into an LDS copy of the BM x BN tile, then every lane stores 16
+    // contiguous bytes, so each output row leaves as whole lines (the direct
+    // 8-byte stores spread over 16 pixels were partial-line writes).
+    constexpr int SP = BN + 8;   // LDS row stride (bf16) of the output tile
+    constexpr bool fits = sizeof(As) >= (size_t)BM * SP * sizeof(bf16);
+    const int cout_up = a.N >> 2;
+    const bool staged = fits && a.out && !a.outf &&
+                        ((a.epi == E_FWD && (a.N & 7) == 0) || (a.epi == E_UPFWD && (cout_up & 7) == 0));
+    if (staged) {
+        bf16* ot = &As[0][0][0];
+        __syncthreads();   // every wave is done with the last chunk's tiles
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+            const int ml = wm * (BM / WGM) + i * 16 + (lane & 15);
+            const long m = m0 + ml;
+#pragma unroll
+            for (int j = 0; j < WTN; ++j) {
+                const int nl = wn * (BN / WGN) + j * 16 + (lane >> 4) * 4, n = n0 + nl;
+                f32x4 v = acc[i][j];
+                if (m < a.M && n < a.N) {
+                    if (a.epi == E_FWD) {
+                        const long pm = m % ((long)a.Ho * a.Wo);
+                        const float4 bb =
+                            a.bmap ? bmap4(a.bmap + pm * a.N + n) : *reinterpret_cast<const float4*>(a.bias + n);
+                        v[0] += bb.x;
+                        v[1] += bb.y;
+                        v[2] += bb.z;
+                        v[3] += bb.w;
+                        if (a.resid) {
+                            const bf16x4g r = *reinterpret_cast<const bf16x4g*>(a.resid + m * a.N + n);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
+                        }
+                    } else {
+                        const float4 bb = *reinterpret_cast<const float4*>(a.bias + (n - (n / cout_up) * cout_up));
+                        v[0] += bb.x;
+                        v[1] += bb.y;
+                        v[2] += bb.z;
+                        v[3] += bb.w;
+                    }
+                    if (a.relu)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                }
+                bf16x4g o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+                *reinterpret_cast<bf16x4g*>(ot + ml * SP + nl) = o;
+            }
+        }
+        __syncthreads();
+        constexpr int CPR = BN / 8;   // 16-byte chunks per tile row
+        for (int k = tid; k < BM * CPR; k += 256) {
+            const int ml = k / CPR, c = k - ml * CPR;
+            const long m = m0 + ml;
+            const int n = n0 + c * 8;
+            if (m >= a.M || n >= a.N) continue;
+            long o;
+            if (a.epi == E_FWD) {
+                o = m * a.N + n;
+            } else {
+                const Pix p = pix_of(m, a.Ho, a.Wo);
+                const int ad = n / cout_up, co = n - ad * cout_up;
+                o = (((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) * cout_up + co;
+            }
+            *reinterpret_cast<bf16x8*>(a.out + o) = *reinterpret_cast<const bf16x8*>(ot + ml * SP + c * 8);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < WTM; ++i) {
         const long m = m0 + wm * (BM / WGM) + i * 16 + (lane & 15);
