@@ -147,6 +147,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
         int nr = a.N - n0 < BN ? a.N - n0 : BN;
         work_atomic(wc, (unsigned long long)(2ull * mr * nr * (unsigned long long)a.kvalid));
     }
+    // the tile's biases (per output channel; an up-convolution's column n uses bias n mod N/4)
+    __shared__ __attribute__((aligned(16))) float bias_s[BN];
+    if (tid < BN && (a.epi == E_FWD || a.epi == E_UPFWD)) {
+        const int n = n0 + tid, nb = a.epi == E_UPFWD ? n % (a.N >> 2 > 0 ? a.N >> 2 : 1) : n;
+        bias_s[tid] = a.bias && n < a.N ? a.bias[nb] : 0.f;
+    }
 
     bf16x8 ra[AS_PER_T], rb[BS_PER_T];
     auto load_chunk = [&](int kc) {
@@ -237,7 +243,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
                     if (a.epi == E_FWD) {
                         const long pm = m % ((long)a.Ho * a.Wo);
                         const float4 bb =
-                            a.bmap ? bmap4(a.bmap + pm * a.N + n) : *reinterpret_cast<const float4*>(a.bias + n);
+                            a.bmap ? bmap4(a.bmap + pm * a.N + n) : *reinterpret_cast<const float4*>(bias_s + nl);
                         v[0] += bb.x;
                         v[1] += bb.y;
                         v[2] += bb.z;
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
                             for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
                         }
                     } else {
-                        const float4 bb = *reinterpret_cast<const float4*>(a.bias + (n - (n / cout_up) * cout_up));
+                        const float4 bb = *reinterpret_cast<const float4*>(bias_s + nl);
                         v[0] += bb.x;
                         v[1] += bb.y;
                         v[2] += bb.z;
@@ -622,19 +628,21 @@ __device__ __forceinline__ void halo_epilogue(const GemmArgs& a, const f32x4 (&a
 }
 
 // Forward epilogue through LDS: each lane finishes its accumulators as above
-// (bias or bias map, residual, ReLU, one rounding to bf16) but writes them to an
-// LDS copy of the block's 16 x 16 x BN output tile; after a barrier every lane
+// (bias or bias map, ReLU, rounding to bf16) but writes them to an LDS copy of
+// the block's 16 x 16 x BN output tile; after a barrier every lane
 // stores 16 contiguous bytes, so a pixel's BN channels leave as whole 64- or
 // 128-byte lines in one instruction instead of four 8-byte pieces per lane
 // spread over 16 pixels (partial-line writes ran at under 2 TB/s).  scratch
-// holds 256 (BN + 8) bf16; every thread of the block must call this.
+// holds 256 (BN + 8) bf16; bias_s holds the block's BN biases (staged into LDS
+// at the start of the kernel, so the epilogue does not wait on a global load);
+// every thread of the block must call this.
 template <int BN>
 __device__ __forceinline__ bool halo_lds_epilogue_ok(const GemmArgs& a) {
     return a.out && !a.outf && (a.N & 7) == 0;
 }
 template <int BN>
 __device__ __forceinline__ void halo_epilogue_lds(const GemmArgs& a, const f32x4 (&acc)[4][BN / 16], int b, int ty0,
-                                                  int tx0, int n0, int tid, bf16* scratch) {
+                                                  int tx0, int n0, int tid, bf16* scratch, const float* bias_s) {
     constexpr int WTN = BN / 16, SP = BN + 8;   // LDS pixel stride (bf16), 16-byte aligned rows
     const int lane = tid & 63, wave = tid >> 6;
     const int x = tx0 + (lane & 15);
@@ -650,17 +658,12 @@ __device__ __forceinline__ void halo_epilogue_lds(const GemmArgs& a, const f32x4
             f32x4 v = acc[i][j];
             if (in && n < a.N) {
                 const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
-                                         : *reinterpret_cast<const float4*>(a.bias + n);
+                                         : *reinterpret_cast<const float4*>(bias_s + nl);
                 v[0] += bb.x;
                 v[1] += bb.y;
                 v[2] += bb.z;
                 v[3] += bb.w;
-                if (a.resid) {
-                    const bf16x4 r = *reinterpret_cast<const bf16x4*>(a.resid + m * a.N + n);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
-                }
-                if (a.relu)
+                if (a.relu && !a.resid)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
             }
@@ -671,15 +674,28 @@ __device__ __forceinline__ void halo_epilogue_lds(const GemmArgs& a, const f32x4
         }
     }
     __syncthreads();
+    // a residual is added here on whole 16-byte rows: convolution plus bias is rounded to bf16
+    // above, the sum with the residual is rounded again
     constexpr int CPP = BN / 8;                   // 16-byte chunks per pixel
 #pragma unroll
     for (int r = 0; r < CPP; ++r) {
         const int k = tid + r * 256;
         const int p = k / CPP, c = k - p * CPP;
         const int y = ty0 + p / HT, xx = tx0 + (p & (HT - 1)), n = n0 + c * 8;
-        if (y < a.Ho && xx < a.Wo && n < a.N)
-            *reinterpret_cast<bf16x8*>(a.out + (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n) =
-                *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
+        if (y < a.Ho && xx < a.Wo && n < a.N) {
+            const long o = (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n;
+            bf16x8 t = *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
+            if (a.resid) {
+                const bf16x8 rr = *reinterpret_cast<const bf16x8*>(a.resid + o);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float w = (float)t[e] + (float)rr[e];
+                    if (a.relu) w = w > 0.f ? w : 0.f;
+                    t[e] = (bf16)w;
+                }
+            }
+            *reinterpret_cast<bf16x8*>(a.out + o) = t;
+        }
     }
     __syncthreads();
 }
@@ -711,6 +727,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN <= 32 ? 
     const int n0 = blockIdx.y * BN;
     if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) return;
     if (tid == 0) halo_count(a, wc, ty0, tx0, n0, BN);
+    __shared__ __attribute__((aligned(16))) float bias_s[BN];
+    if (EPI == E_FWD && tid < BN) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[n0 + tid] : 0.f;
     f32x4 acc[4][WTN];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -732,7 +750,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN <= 32 ? 
     }
     static_assert(sizeof(Ws) >= 256 * (BN + 8) * sizeof(bf16), "epilogue scratch");
     if (EPI == E_FWD && halo_lds_epilogue_ok<BN>(a))
-        halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ws[0][0][0]);
+        halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ws[0][0][0], bias_s);
     else
         halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 }
@@ -759,6 +777,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 1 ? 
     };
     int t = next_tile(blockIdx.x);
     if (t >= ntiles) return;   // the same decision for every thread of the block
+    __shared__ __attribute__((aligned(16))) float bias_s[BN];
+    if (EPI == E_FWD && tid < BN) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[n0 + tid] : 0.f;
     // all weights of the block's output channels, once
     constexpr int C = NCH * HC;
     for (int sg = tid; sg < 9 * BN * (C / 8); sg += 256) {
@@ -793,7 +813,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 1 ? 
             work += halo_work(a, ty0, tx0, n0, BN);
             constexpr bool fits = sizeof(Ps) >= 256 * (BN + 8) * sizeof(bf16);
             if (EPI == E_FWD && fits && halo_lds_epilogue_ok<BN>(a))
-                halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ps[0][0]);
+                halo_epilogue_lds<BN>(a, acc, b, ty0, tx0, n0, tid, &Ps[0][0], bias_s);
             else
                 halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 #pragma unroll
