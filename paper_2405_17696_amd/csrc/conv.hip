@@ -116,6 +116,7 @@ __device__ __forceinline__ bf16x8 gather8(const GemmArgs& a, long m, int k0) {
 }
 
 typedef __bf16 bf16x4g __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2g __attribute__((ext_vector_type(2)));
 constexpr int KC = 32;      // k per chunk
 constexpr int LDS_K = 40;   // padded row length (bf16) of the LDS tiles
 
@@ -922,6 +923,11 @@ __global__ __launch_bounds__(256) void k_conv3_first2(GemmArgs a, unsigned long 
     for (int j = 0; j < NT; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) bias[j][e] = a.bias[j * 16 + kg * 4 + e];
+    // per-wave LDS rows for whole-line stores: N = 16 NT channels per pixel, padded
+    constexpr int FSP = NT * 16 + 8;
+    __shared__ __attribute__((aligned(16))) bf16 fl[4][16 * FSP];
+    bf16* wl = fl[threadIdx.x >> 6];
+    const bool staged = a.out && !a.outf && !a.resid && a.N == NT * 16;
     unsigned long long work = 0;
     for (long sgi = wave0; sgi < nseg; sgi += nwaves) {
         const int sx = (int)(sgi % segs_x);
@@ -937,13 +943,42 @@ __global__ __launch_bounds__(256) void k_conv3_first2(GemmArgs a, unsigned long 
             if (tap >= 9) break;
             const int yi = y + tap / 3 - 1, xi = x + tap % 3 - 1;
             if (x < a.Wo && yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi) {
+                // both channels of the tap in one 4-byte load
                 const bf16* src = a.a1 + b * a.abs1 + ((long)yi * a.Wi + xi) * 2;
-                fx[2 * q] = src[0];
-                fx[2 * q + 1] = src[1];
+                const bf16x2g v2 = *reinterpret_cast<const bf16x2g*>(src);
+                fx[2 * q] = v2[0];
+                fx[2 * q + 1] = v2[1];
             }
         }
         if (x < a.Wo) work += 2ull * 18 * a.N;
         const long m = ((long)b * a.Ho + y) * a.Wo + x;
+        if (staged) {
+            // the segment's 16 pixels x N channels are contiguous in memory: finish them
+            // into the wave's LDS rows and store 16 contiguous bytes per lane
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const f32x4 acc =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fx, (f32x4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                bf16x4g o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[e] + bias[j][e];
+                    if (a.relu) v = v > 0.f ? v : 0.f;
+                    o[e] = (bf16)v;
+                }
+                *reinterpret_cast<bf16x4g*>(wl + (lane & 15) * FSP + j * 16 + kg * 4) = o;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const long m0 = ((long)b * a.Ho + y) * a.Wo + sx * 16;
+            for (int k = lane; k < 16 * (NT * 2); k += 64) {
+                const int px = k / (NT * 2), c = k - px * (NT * 2);
+                if (sx * 16 + px < a.Wo)
+                    *reinterpret_cast<bf16x8*>(a.out + (m0 + px) * a.N + c * 8) =
+                        *reinterpret_cast<const bf16x8*>(wl + px * FSP + c * 8);
+            }
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fx, (f32x4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -1018,6 +1053,8 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
     };
     int t = next_tile(blockIdx.x);
     if (t >= ntiles) return;   // the same decision for every thread of the block
+    __shared__ float bl[2][32];   // both layers' biases, read from LDS in every tile's epilogues
+    if (tid < 64) bl[tid >> 5][tid & 31] = (tid < 32 ? a.b1 : a.b2)[tid & 31];
     for (int sg = tid; sg < 9 * 32 * 4; sg += 256) {
         const int row = sg >> 2, sub = sg & 3, tap = row >> 5, n = row & 31;
         *reinterpret_cast<bf16x8*>(&W1s[tap][n][sub * 8]) = ld8(a.w1 + (long)n * a.K1 + tap * 32 + sub * 8);
@@ -1079,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
                 bf16x4r hv;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const float v = acc[i][j][e] + a.b1[n + e];
+                    const float v = acc[i][j][e] + bl[0][n + e];
                     hv[e] = (bf16)(in && v > 0.f ? v : 0.f);
                 }
                 *reinterpret_cast<bf16x4r*>(&Ps[(py + 1) * HP + px + 1][n]) = hv;
@@ -1120,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
                 const int n = j * 16 + (lane >> 4) * 4;
                 bf16x4r o;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) o[e] = (bf16)(acc[i][j][e] + a.b2[n + e] + (float)res[i][j][e]);
+                for (int e = 0; e < 4; ++e) o[e] = (bf16)(acc[i][j][e] + bl[1][n + e] + (float)res[i][j][e]);
                 *reinterpret_cast<bf16x4r*>(ob + ((py - 1) * RT + px - 1) * OSP + n) = o;
             }
         }
