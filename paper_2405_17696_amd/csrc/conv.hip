@@ -130,8 +130,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
     constexpr int BSEG = BN * KC / 8;
     constexpr int AS_PER_T = (ASEG + 255) / 256;
     constexpr int BS_PER_T = (BSEG + 255) / 256;
-    __shared__ __attribute__((aligned(16))) bf16 As[2][BM][LDS_K];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN][LDS_K];
+    // one LDS buffer: the double-buffered A and B tiles, reused by the epilogue
+    __shared__ __attribute__((aligned(16))) bf16 smem[2 * (BM + BN) * LDS_K];
+    bf16 (*As)[BM][LDS_K] = reinterpret_cast<bf16 (*)[BM][LDS_K]>(smem);
+    bf16 (*Bs)[BN][LDS_K] = reinterpret_cast<bf16 (*)[BN][LDS_K]>(smem + 2 * BM * LDS_K);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const long m0 = (long)blockIdx.x * BM;
@@ -225,12 +227,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, unsigned long long* wc
     // contiguous bytes, so each output row leaves as whole lines (the direct
     // 8-byte stores spread over 16 pixels were partial-line writes).
     constexpr int SP = BN + 8;   // LDS row stride (bf16) of the output tile
-    constexpr bool fits = sizeof(As) >= (size_t)BM * SP * sizeof(bf16);
+    constexpr bool fits = sizeof(smem) >= (size_t)BM * SP * sizeof(bf16);
     const int cout_up = a.N >> 2;
     const bool staged = fits && a.out && !a.outf &&
                         ((a.epi == E_FWD && (a.N & 7) == 0) || (a.epi == E_UPFWD && (cout_up & 7) == 0));
     if (staged) {
-        bf16* ot = &As[0][0][0];
+        bf16* ot = smem;
         __syncthreads();   // every wave is done with the last chunk's tiles
 #pragma unroll
         for (int i = 0; i < WTM; ++i) {
@@ -1229,11 +1231,14 @@ static void launch_gemm_tile(const GemmArgs& a, hipStream_t s, unsigned long lon
 }
 
 template <int GM>
-static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long long* wc, bool tall) {
-    if (tall)
-        launch_gemm_tile<GM, 128, 32, 4, 1>(a, s, wc);
-    else
-        launch_gemm_tile<GM, 64, 64, 2, 2>(a, s, wc);
+// Block tiles: 0: 64 x 64, 1: 128 x 32, 2: 64 x 128, 3: 128 x 64 (pixels x output columns).
+static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long long* wc, int shape) {
+    switch (shape) {
+        case 1: launch_gemm_tile<GM, 128, 32, 4, 1>(a, s, wc); break;
+        case 2: launch_gemm_tile<GM, 64, 128, 2, 2>(a, s, wc); break;
+        case 3: launch_gemm_tile<GM, 128, 64, 2, 2>(a, s, wc); break;
+        default: launch_gemm_tile<GM, 64, 64, 2, 2>(a, s, wc); break;
+    }
 }
 
 // ------------------------------------------------------------------ kernel choice and autotuning
@@ -1242,7 +1247,9 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // (outside stream capture) times every applicable candidate on the caller's
 // buffers and keeps the fastest for that shape.  Only overwriting epilogues are
 // tuned (accumulating ones would add each candidate's result).
-enum ConvKernel { CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_COUNT };
+enum ConvKernel {
+    CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W, CK_COUNT
+};
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
     const bool halo = halo_ok(a);
@@ -1253,6 +1260,8 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_HALO64: return halo;
         case CK_GEMM64:
         case CK_GEMM128: return true;
+        case CK_GEMM64W: return a.N >= 128;
+        case CK_GEMM128W: return a.N >= 64;
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1316,12 +1325,12 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
             break;
         }
         default: {
-            const bool tall = ck == CK_GEMM128;
+            const int shape = ck == CK_GEMM128 ? 1 : ck == CK_GEMM64W ? 2 : ck == CK_GEMM128W ? 3 : 0;
             switch (a.gmode) {
-                case G_CONV: launch_gemm_pick<G_CONV>(a, s, wc, tall); break;
-                case G_CONVT: launch_gemm_pick<G_CONVT>(a, s, wc, tall); break;
-                case G_UP: launch_gemm_pick<G_UP>(a, s, wc, tall); break;
-                case G_UPT: launch_gemm_pick<G_UPT>(a, s, wc, tall); break;
+                case G_CONV: launch_gemm_pick<G_CONV>(a, s, wc, shape); break;
+                case G_CONVT: launch_gemm_pick<G_CONVT>(a, s, wc, shape); break;
+                case G_UP: launch_gemm_pick<G_UP>(a, s, wc, shape); break;
+                case G_UPT: launch_gemm_pick<G_UPT>(a, s, wc, shape); break;
                 default: return fail(HELM_EINVAL, "gemm: gather mode %d", a.gmode);
             }
         }
