@@ -240,11 +240,11 @@ int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsr
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
  * times every applicable kernel (halo-tiled persistent / one tile per block,
- * 32 or 64 output channels per block, implicit GEMM with 64x64 or 128x32
- * tiles, the direct first-layer kernel) on the caller's buffers and keeps the
- * fastest for that shape for the rest of the process; launches inside a
- * stream capture use the built-in rule until the shape has been tuned
- * eagerly.  enable: 1 on, 0 off (built-in rule only), 2 forget the tuned
+ * 32 or 64 output channels per block, implicit GEMM with 64x64, 128x32,
+ * 64x128 or 128x64 tiles, the direct first-layer kernel) on the caller's
+ * buffers and keeps the fastest for that shape for the rest of the process;
+ * launches inside a stream capture use the built-in rule until the shape has
+ * been tuned eagerly.  enable: 1 on, 0 off (built-in rule only), 2 forget the tuned
  * shapes, -1 leave unchanged.  tuned_shapes (host, may be NULL): number of
  * shapes tuned so far.
  */
@@ -253,6 +253,13 @@ int helm_autotune(int enable, int* tuned_shapes);
  * table) a text file (host path), so that another process launches exactly the
  * same kernels for the same shapes. */
 int helm_autotune_file(const char* path, int save);
+/* Diagnostics: pin the convolution kernel.  kernel in 0 .. kernel_count - 1 makes
+ * every convolution launch for which that kernel applies use it (bypassing the
+ * autotuner and the built-in rule; launches it does not apply to keep their
+ * usual choice); -1 removes the pin.  kernel_count (host, may be NULL) receives
+ * the number of kernel kinds.  For tests that check each kernel against a
+ * reference; EINVAL for an id outside -1 .. kernel_count - 1. */
+int helm_conv_force(int kernel, int* kernel_count);
 
 /*
  * Diagnostics: time every launch of one named kernel ("k_matvec_dot",

@@ -83,6 +83,7 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p]),
     "helm_autotune": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
     "helm_autotune_file": (C.c_int, [C.c_char_p, C.c_int]),
+    "helm_conv_force": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
     "fwi_misfit_grad": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
                                   C.POINTER(C.c_int), C.c_int, C.c_void_p, C.c_double, C.POINTER(SolveOpts),
                                   C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_int), C.c_void_p]),

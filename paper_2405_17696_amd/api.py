@@ -144,6 +144,14 @@ def helm_autotune(enable: int = -1) -> int:
     return n.value
 
 
+def helm_conv_force(kernel: int = -1) -> int:
+    """Pin the convolution kernel (an id below the returned count) wherever it
+    applies, or remove the pin with -1.  Returns the number of kernel kinds."""
+    n = C.c_int()
+    L.check(L.load().helm_conv_force(int(kernel), C.byref(n)))
+    return n.value
+
+
 def helm_autotune_file(path, save: bool):
     """Save the tuned convolution kernel choices to, or merge them from, a text file."""
     L.check(L.load().helm_autotune_file(str(path).encode(), int(save)))

@@ -1778,6 +1778,8 @@ extern "C" int helm_autotune(int enable, int* tuned_shapes) {
     return conv_autotune(enable, tuned_shapes);
 }
 
+extern "C" int helm_conv_force(int kernel, int* kernel_count) { return conv_force(kernel, kernel_count); }
+
 extern "C" int helm_autotune_file(const char* path, int save) {
     if (!path) return fail(HELM_EINVAL, "helm_autotune_file: path is NULL");
     return conv_autotune_file(path, save);

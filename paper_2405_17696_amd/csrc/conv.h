@@ -91,6 +91,7 @@ int launch_resblock32(const ResArgs& a, hipStream_t s);
 // enable: 1 on, 0 off (built-in rule), 2 forget the tuned shapes; -1 query only.
 int conv_autotune(int enable, int* tuned);
 int conv_autotune_file(const char* path, int save);
+int conv_force(int kernel, int* count);
 // Weight gradient into at most max_split partial slabs [M][Npad] at a.part;
 // *nsplit receives the number written (a.pchunk is chosen here).
 int launch_wgrad(WgradArgs a, int max_split, hipStream_t s, int* nsplit);

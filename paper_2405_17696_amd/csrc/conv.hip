@@ -1351,6 +1351,7 @@ struct TuneKey {
 std::map<TuneKey, int> g_tuned;
 std::mutex g_tune_mutex;
 bool g_tune_on = true;
+int g_force = -1;   // pinned kernel (where applicable), -1 for none
 
 TuneKey tune_key(const GemmArgs& a) {
     TuneKey k{};
@@ -1415,7 +1416,14 @@ int launch_gemm(const GemmArgs& a, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0) return HELM_OK;
     int ck = ck_default(a);
     const bool tunable = (a.epi == E_FWD || a.epi == E_UPFWD) && a.out != nullptr;
-    if (tunable) {
+    int forced = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        forced = g_force;
+    }
+    if (forced >= 0 && ck_applicable(a, forced)) {
+        ck = forced;
+    } else if (tunable) {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         if (g_tune_on) {
             const TuneKey key = tune_key(a);
@@ -1461,6 +1469,15 @@ int conv_autotune_file(const char* path, int save) {
         g_tuned[k] = ck;
     }
     fclose(f);
+    return HELM_OK;
+}
+
+int conv_force(int kernel, int* count) {
+    if (count) *count = CK_COUNT;
+    if (kernel < -1 || kernel >= CK_COUNT)
+        return fail(HELM_EINVAL, "helm_conv_force: kernel %d outside -1 .. %d", kernel, CK_COUNT - 1);
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_force = kernel;
     return HELM_OK;
 }
 

@@ -131,3 +131,52 @@ def test_fused_resblock32(gpu, B, H, W_):
     h = bf(np.maximum(U.conv3x3(x, W1, b1, 1), 0))       # the kernel keeps h in BF16
     ref = x + U.conv3x3(h, W2, b2, 1)
     assert relerr(y, ref) <= 5e-3                         # output stored in BF16
+
+
+FORCE_CASES = [
+    # name, kind, stride, B, H, W, c1, c2, bcast2, cout, relu, resid
+    ("s1_tiles", 0, 1, 2, 37, 50, 64, 0, False, 64, True, False),
+    ("s1_n128", 0, 1, 1, 20, 18, 32, 0, False, 128, True, False),
+    ("concat", 0, 1, 2, 18, 20, 32, 32, False, 32, True, False),
+    ("ctx", 0, 1, 2, 17, 16, 32, 32, True, 64, True, False),
+    ("resid", 0, 1, 1, 18, 31, 128, 0, False, 128, False, True),
+    ("head", 0, 1, 2, 20, 24, 32, 0, False, 2, False, False),
+    ("first", 0, 1, 2, 16, 20, 2, 0, False, 32, True, False),
+    ("s2", 0, 2, 2, 20, 18, 64, 0, False, 128, True, False),
+    ("s2_wide", 0, 2, 1, 16, 16, 128, 0, False, 256, True, False),
+    ("up", 1, 2, 2, 9, 10, 128, 0, False, 64, True, False),
+    ("up_wide", 1, 2, 1, 8, 8, 256, 0, False, 128, True, False),
+]
+
+
+def test_every_convolution_kernel_against_oracle(gpu):
+    """Each convolution kernel kind, pinned in turn, on every layer shape it
+    applies to (stride 1 and 2, concatenated and broadcast context, residual,
+    2-channel head, first layer, up-convolution, ragged 16 x 16 tiles) against
+    the oracle's direct convolution."""
+    count = api.helm_conv_force(-1)
+    assert count >= 9
+    try:
+        for k in range(count):
+            api.helm_conv_force(k)
+            for name, kind, s, B, H, W_, c1, c2, bc, cout, relu, use_resid in FORCE_CASES:
+                print("kernel", k, "case", name, flush=True)
+                if kind == 1:
+                    x = rnd((B, H, W_, c1), 21)
+                    Wt = rnd((2, 2, cout, c1), 22, scale=np.sqrt(2.0 / c1))
+                    b = rnd((cout,), 23, 0.1)
+                    y = api.cnn_layer_forward(1, 2, x, Wt, b, relu=True)
+                    assert relerr(y, np.maximum(U.upconv(x, Wt, b), 0)) <= 5e-3
+                    continue
+                x1 = rnd((B, H, W_, c1), 24)
+                x2 = rnd(((1 if bc else B), H, W_, c2), 25) if c2 else None
+                Wt = rnd((cout, 3, 3, c1 + c2), 26, scale=np.sqrt(2.0 / (9 * (c1 + c2))))
+                b = rnd((cout,), 27, 0.1)
+                Ho, Wo = (H + s - 1) // s, (W_ + s - 1) // s
+                resid = rnd((B, Ho, Wo, cout), 28) if use_resid else None
+                y = api.cnn_layer_forward(0, s, x1, Wt, b, x2=x2, bcast2=bc, resid=resid, relu=relu)
+                assert relerr(y, ref_conv(x1, x2, Wt, b, s, bc, relu, resid)) <= 1e-5
+    finally:
+        api.helm_conv_force(-1)
+    with pytest.raises(Exception):
+        api.helm_conv_force(count)
