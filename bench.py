@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--save-net", default=None, help="write the trained network to this file")
     ap.add_argument("--no-compare", action="store_true", help="skip the graph-replay and MG comparison runs")
     ap.add_argument("--kernel", default=None, help="kernel whose roofline is reported")
+    ap.add_argument("--sample-every", type=int, default=8,
+                    help="time and count every n-th launch of that kernel (event packets between all launches "
+                         "slow the timed solve by ~7%%)")
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
@@ -89,18 +92,21 @@ def measured_traffic():
         return None
 
 
-def kernel_roofline(api_lib, name):
+def kernel_roofline(api_lib, name, every):
+    """Average event-timed duration and algorithmic work of the sampled launches
+    (every every-th launch of the family in the timed region)."""
     import ctypes as C
     n = C.c_int()
     ms = C.c_double()
     work = C.c_double()
+    total = C.c_longlong()
     rc = api_lib.helm_ktimer_read(C.byref(n), C.byref(ms), C.byref(work))
-    if rc != 0 or n.value == 0 or ms.value <= 0:
+    if rc != 0 or n.value == 0 or ms.value <= 0 or api_lib.helm_ktimer_count(C.byref(total)) != 0:
         return None
     avg_ms = ms.value / n.value
     achieved = work.value / (ms.value * 1e-3) / 1e9
-    return {"kernel": name, "launches": n.value, "avg_us": avg_ms * 1e3, "achieved": achieved,
-            "work_per_launch": work.value / n.value}
+    return {"kernel": name, "launches": total.value, "sampled_launches": n.value, "sampled_every": every,
+            "avg_us": avg_ms * 1e3, "achieved": achieved, "work_per_launch": work.value / n.value}
 
 
 def cpu_baseline(med, src, nrhs):
@@ -215,13 +221,14 @@ def main_c2(a):
         torch.cuda.synchronize()
         if timer:
             _lib.check(lib.helm_ktimer_start(timer.encode()))
+            _lib.check(lib.helm_ktimer_sample(a.sample_every))
         t0 = time.perf_counter()
         last = None
         for _ in range(steps):
             last = step(pc, restart, use_graph)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        roof = kernel_roofline(lib, timer) if timer else None
+        roof = kernel_roofline(lib, timer, a.sample_every) if timer else None
         if timer:
             _lib.check(lib.helm_ktimer_start(None))
         return dt, last, roof
@@ -258,11 +265,13 @@ def main_c2(a):
                     "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
                     "traffic": measured_traffic() if precond == "cnn_vu" and restart == 10 else None,
                     "avg_us": roof["avg_us"], "launches": roof["launches"],
+                    "sampled_launches": roof["sampled_launches"], "sampled_every": roof["sampled_every"],
                     "flops_per_launch": roof["work_per_launch"]}
     elif roof:
         roofline = {"bound": "hbm", "kernel": roof["kernel"], "achieved": roof["achieved"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": roof["achieved"] / HBM_PEAK_GBS, "traffic": None,
                     "avg_us": roof["avg_us"], "launches": roof["launches"],
+                    "sampled_launches": roof["sampled_launches"], "sampled_every": roof["sampled_every"],
                     "bytes_per_launch": roof["work_per_launch"]}
     cpu = None
     if not a.no_cpu_baseline:

@@ -262,17 +262,25 @@ int helm_autotune_file(const char* path, int save);
 int helm_conv_force(int kernel, int* kernel_count);
 
 /*
- * Diagnostics: time every launch of one named kernel ("k_matvec_dot",
- * "k_update", "k_mg_down", "k_mg_up", "k_poly_term", "k_true_residual",
- * "k_conv_fwd", ...) with HIP events recorded on the stream it is launched on,
- * and count the algorithmic bytes (or flops) its active blocks processed.
- * Launches inside a captured restart-cycle graph are timed too: the events
- * become event-record nodes of the graph and are read after every replay.
- * kernel = NULL stops timing.  helm_ktimer_read synchronises the device and
- * returns the totals since the last start (host outputs).
+ * Diagnostics: time the launches of one named kernel family ("k_matvec_dot",
+ * "k_update", "k_mg_down", "k_mg_up", "k_poly_lds", "k_conv", ...) with
+ * fence-free HIP events recorded on the stream each is launched on, and count
+ * the algorithmic bytes (or flops) their active blocks processed.  Launches
+ * recorded into a stream capture are neither timed nor counted (a replayed
+ * graph has no per-launch events).  kernel = NULL stops timing.
+ * helm_ktimer_sample(every) samples only every every-th launch of the family
+ * (from the first after helm_ktimer_start; default 1 = all), which keeps the
+ * event packets from slowing a long run; time and work are then both taken
+ * over the sampled launches.  helm_ktimer_read synchronises the device and
+ * returns the sampled launches, their total event time and their total work
+ * since the last start (host outputs).
  */
 int helm_ktimer_start(const char* kernel);
+int helm_ktimer_sample(int every);
 int helm_ktimer_read(int* launches, double* total_ms, double* total_work);
+/* All eager launches of the named family since helm_ktimer_start, sampled or
+ * not (host output). */
+int helm_ktimer_count(long long* launches);
 
 const char* helm_last_error(void);
 /* Library version string. */

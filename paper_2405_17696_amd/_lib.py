@@ -92,6 +92,8 @@ SIGNATURES = {
     "cnn_layer_forward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 5 + [C.c_int, C.c_void_p]),
     "cnn_layer_backward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 4 + [C.c_int] + [C.c_void_p] * 5),
     "helm_ktimer_start": (C.c_int, [C.c_char_p]),
+    "helm_ktimer_sample": (C.c_int, [C.c_int]),
+    "helm_ktimer_count": (C.c_int, [C.POINTER(C.c_longlong)]),
     "helm_ktimer_read": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "helm_last_error": (C.c_char_p, []),
     "helm_version": (C.c_char_p, []),

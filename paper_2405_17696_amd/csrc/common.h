@@ -28,11 +28,16 @@ int fail(int code, const char* fmt, ...);
 #define HELM_CHECK_LAUNCH() HELM_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------- kernel timer
-// When a kernel name is armed, its launchers bracket each launch with events on
-// the launch stream and pass a device counter that active blocks add their
-// algorithmic work (bytes or flops) to.
+// When a kernel name is armed, its launchers bracket each sampled launch (every
+// launch, or every period-th one) with events on the launch stream and pass a
+// device counter that the sampled launch's active blocks add their algorithmic
+// work (bytes or flops) to.
 struct KTimer {
+    // true when this launch of the named kernel is sampled (timed and counted)
     bool armed(const char* name) const;
+    // after every launch of the named kernel: advance the launch count and decide
+    // whether the next launch is sampled (every period-th launch is)
+    void next(const char* name, hipStream_t s);
     unsigned long long* counter() const;
     bool capturing(hipStream_t s) const;
     void begin(hipStream_t s);
@@ -51,6 +56,7 @@ KTimer& ktimer();
         if (on_) ::helm::ktimer().begin(stream);                \
         hipLaunchKernelGGL(__VA_ARGS__);                        \
         if (on_) ::helm::ktimer().end(stream);                  \
+        ::helm::ktimer().next(name, stream);                    \
     } while (0)
 
 // Launches recorded into a graph are neither timed nor counted.

@@ -15,6 +15,9 @@ struct TimerState {
     size_t used = 0;
     unsigned long long* dcount = nullptr;
     hipEvent_t pending = nullptr;
+    int period = 1;            // every period-th launch is sampled
+    long long launches = 0;    // launches of the named kernel since the start
+    bool sample = true;        // whether the next launch is sampled
 };
 TimerState g_t;
 
@@ -30,7 +33,8 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool KTimer::armed(const char* name) const { return !g_t.name.empty() && g_t.name == name; }
+static bool named(const char* name) { return !g_t.name.empty() && g_t.name == name; }
+bool KTimer::armed(const char* name) const { return named(name) && g_t.sample; }
 unsigned long long* KTimer::counter() const { return g_t.dcount; }
 static bool stream_capturing(hipStream_t s) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -51,6 +55,11 @@ void KTimer::end(hipStream_t s) {
     if (e && hipEventRecord(e, s) == hipSuccess) g_t.ev.push_back({g_t.pending, e});
     g_t.pending = nullptr;
 }
+void KTimer::next(const char* name, hipStream_t s) {
+    if (!named(name) || stream_capturing(s)) return;
+    ++g_t.launches;
+    g_t.sample = g_t.launches % g_t.period == 0;
+}
 void KTimer::replayed() {}
 void KTimer::harvest() {}
 void KTimer::new_capture() {}
@@ -68,6 +77,8 @@ extern "C" int helm_ktimer_start(const char* kernel) {
     g_t.ev.clear();
     g_t.used = 0;
     g_t.name = kernel ? kernel : "";
+    g_t.launches = 0;
+    g_t.sample = true;
     if (kernel) {
         const size_t bytes = sizeof(unsigned long long) * WORK_SLOTS * WORK_SLOT_STRIDE;
         if (!g_t.dcount && hipMalloc(&g_t.dcount, bytes) != hipSuccess)
@@ -75,6 +86,18 @@ extern "C" int helm_ktimer_start(const char* kernel) {
         if (hipMemset(g_t.dcount, 0, bytes) != hipSuccess)
             return fail(HELM_EHIP, "helm_ktimer_start: counter reset failed");
     }
+    return HELM_OK;
+}
+
+extern "C" int helm_ktimer_sample(int every) {
+    if (every < 1) return fail(HELM_EINVAL, "helm_ktimer_sample: every must be >= 1, got %d", every);
+    g_t.period = every;
+    return HELM_OK;
+}
+
+extern "C" int helm_ktimer_count(long long* launches) {
+    if (!launches) return fail(HELM_EINVAL, "helm_ktimer_count: NULL output");
+    *launches = g_t.launches;
     return HELM_OK;
 }
 
