@@ -144,9 +144,14 @@ def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=
     lr0/2 up to 3000, lr0/4 after).  Every eval_every steps the network is
     scored by the mean CNN-FGMRES iteration count on 8 validation sources (row
     24, not the workload's row-4 sources) and the best-scoring weights are kept:
-    the training loss is a poor proxy for the preconditioner's quality."""
+    the training loss is a poor proxy for the preconditioner's quality.
+    Training runs with the built-in kernel choice (autotuning off), so that the
+    trained network, and with it the iteration count, does not depend on which
+    kernels the timing-based autotuner happened to pick (they round differently,
+    and the training trajectory amplifies that); autotuning is restored after."""
     import torch
     from paper_2405_17696_amd import synth
+    api.helm_autotune(0)
     op_t = api.helm_setup(k2, gam, med.omega, med.h)
     n = med.kappa2.shape[0]
     vsrc = synth.point_sources(n, n, synth.surface_positions(n, 8), row=24, h=med.h)
@@ -172,6 +177,7 @@ def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=
     torch.cuda.synchronize()
     tt = time.perf_counter() - t0
     op_t.close()
+    api.helm_autotune(1)
     return {"steps": steps, "batch": 16, "pairs_per_round": 2048, "seconds": tt,
             "ms_per_step_incl_data_and_validation": 1e3 * tt / max(1, steps),
             "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:])),
