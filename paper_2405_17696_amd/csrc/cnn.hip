@@ -654,9 +654,56 @@ static bool fusable_resblock(const cnn_net* net, const Arena& A, const Program& 
     return x.C == 32 && h.C == 32 && y.C == 32 && net->layers[a.layer].K >= 288 && net->layers[b.layer].K >= 288;
 }
 
+// The solver's first layer (2 -> 32 channels) followed by the level-0 context
+// convolution in its split form, with nothing else reading the first layer's
+// output: one fused kernel at inference.
+static bool fusable_first_ctx(const cnn_net* net, const Arena& A, const Program& P, size_t oi) {
+    if (A.train || !A.ctx || oi + 1 >= P.ops.size()) return false;
+    const Op& a = P.ops[oi];
+    const Op& b = P.ops[oi + 1];
+    if (a.kind != OP_CONV || b.kind != OP_CONV || a.stride != 1 || b.stride != 1) return false;
+    if (!a.relu || !b.relu || a.resid >= 0 || b.resid >= 0 || a.in2 != -1 || b.in1 != a.out || b.out == P.output)
+        return false;
+    const LayerDesc& Lb = net->layers[b.layer];
+    if (!(Lb.ctx && b.bcast2 && b.in2 <= -2)) return false;
+    for (size_t j = oi + 2; j < P.ops.size(); ++j) {
+        const Op& o = P.ops[j];
+        if (o.in1 == a.out || o.in2 == a.out || o.resid == a.out) return false;
+    }
+    const Tens& x = tens_of(A, P, a.in1);
+    const Tens& h = P.t[a.out];
+    const Tens& y = P.t[b.out];
+    return x.C == 2 && h.C == 32 && y.C == 32 && x.H == y.H && x.W == y.W && x.B == y.B &&
+           net->layers[a.layer].K >= 32 && Lb.Kh >= 288;
+}
+
 static int run_forward(const cnn_net* net, Arena& A, Program& P, const RhsState* st, int rhs0, hipStream_t s) {
     for (size_t oi = 0; oi < P.ops.size(); ++oi) {
         const Op& op = P.ops[oi];
+        if (fusable_first_ctx(net, A, P, oi)) {
+            const Op& o2 = P.ops[oi + 1];
+            const LayerDesc& L0 = net->layers[op.layer];
+            const LayerDesc& L1 = net->layers[o2.layer];
+            const Tens& x = tens_of(A, P, op.in1);
+            FirstCtxArgs f{};
+            f.r = x.d;
+            f.B = x.B;
+            f.H = x.H;
+            f.W = x.W;
+            f.w0 = net->wb + L0.wb_off;
+            f.K0 = L0.K;
+            f.b0 = net->master + L0.boff;
+            f.wh = net->wb + L1.wh_off;
+            f.Kh = L1.Kh;
+            f.bmap = A.ctx->zc[-o2.in2 - 2];
+            f.out = P.t[o2.out].d;
+            f.st = (&P == &A.sol) ? st : nullptr;
+            f.rhs0 = rhs0;
+            int rc = launch_first_ctx(f, s);
+            if (rc) return rc;
+            ++oi;
+            continue;
+        }
         if (fusable_resblock(net, A, P, oi)) {
             const Op& o2 = P.ops[oi + 1];
             const LayerDesc& L1 = net->layers[op.layer];

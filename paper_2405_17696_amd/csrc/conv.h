@@ -88,6 +88,24 @@ struct ResArgs {
     int rhs0;
 };
 int launch_resblock32(const ResArgs& a, hipStream_t s);
+
+// Fused first layer and level-0 context convolution of the solver (inference):
+// out = ReLU(conv_h(h0) + bmap) with h0 = ReLU(conv0(r) + b0) computed per tile
+// in LDS, so h0 never goes to memory.  r has 2 channels, h0 and out 32.
+struct FirstCtxArgs {
+    const bf16* r;       // [B][H][W][2]
+    int B, H, W;
+    const bf16* w0;      // first layer [32][K0], k = tap * 2 + c (K0 >= 32, zero past 18)
+    int K0;
+    const float* b0;     // [32]
+    const bf16* wh;      // the context convolution's h part [32][Kh], k = tap * 32 + c
+    int Kh;
+    const bf16* bmap;    // [H][W][32]: its z part plus bias, per pixel
+    bf16* out;           // [B][H][W][32]
+    const RhsState* st;  // optional: skip samples whose RHS is inactive
+    int rhs0;
+};
+int launch_first_ctx(const FirstCtxArgs& a, hipStream_t s);
 // enable: 1 on, 0 off (built-in rule), 2 forget the tuned shapes; -1 query only.
 int conv_autotune(int enable, int* tuned);
 int conv_autotune_file(const char* path, int save);

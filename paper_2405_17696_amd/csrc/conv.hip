@@ -1182,6 +1182,136 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
     if (wc && tid == 0) work_atomic(wc, work);
 }
 
+// Solver first layer + level-0 context convolution in one persistent kernel.
+// Per 16 x 16 output tile: the 20 x 20 two-channel input patch goes to LDS, the
+// 18 x 18 h0 patch is computed from it with one 32-deep MFMA step per 16 pixels
+// (first layer weights in registers, taps 9..15 of the K step zero) and written
+// to the patch buffer (zero outside the image: the context convolution's
+// padding), then the context convolution runs on it as in the halo kernels.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_first_ctx(FirstCtxArgs a,
+                                                                                         unsigned long long* wc) {
+    constexpr int RP = HT + 4;   // input patch edge
+    __shared__ __attribute__((aligned(16))) bf16 Ps[HP * HP][HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[9][32][HLD];
+    __shared__ unsigned Rs[RP * RP];   // two bf16 channels per pixel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (a.W + HT - 1) / HT, tiles_y = (a.H + HT - 1) / HT, tps = tiles_x * tiles_y;
+    const int ntiles = a.B * tps;
+    auto next_tile = [&](int t) {
+        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+            t += gridDim.x;
+        return t;
+    };
+    int t = next_tile(blockIdx.x);
+    if (t >= ntiles) return;   // the same decision for every thread of the block
+    for (int sg = tid; sg < 9 * 32 * 4; sg += 256) {
+        const int row = sg >> 2, sub = sg & 3, tap = row >> 5, n = row & 31;
+        *reinterpret_cast<bf16x8*>(&Ws[tap][n][sub * 8]) = ld8(a.wh + (long)n * a.Kh + tap * 32 + sub * 8);
+    }
+    const int kg = lane >> 4;   // this lane's k = 8 kg .. 8 kg + 7: taps 4 kg .. 4 kg + 3, two channels each
+    bf16x8 fw[2];
+    float b0v[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        fw[j] = ld8(a.w0 + (long)(j * 16 + (lane & 15)) * a.K0 + kg * 8);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b0v[j][e] = a.b0[j * 16 + kg * 4 + e];
+    }
+    auto origin = [&](int tt, int& b, int& ty0, int& tx0) {
+        b = tt / tps;
+        ty0 = ((tt / tiles_x) % tiles_y) * HT;
+        tx0 = (tt % tiles_x) * HT;
+    };
+    unsigned rr[2];
+    auto rload = [&](int tt) {
+        int b, ty0, tx0;
+        origin(tt, b, ty0, tx0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = tid + q * 256;
+            const int py = idx / RP, px = idx - py * RP;
+            const int yi = ty0 - 2 + py, xi = tx0 - 2 + px;
+            rr[q] = idx < RP * RP && yi >= 0 && yi < a.H && xi >= 0 && xi < a.W
+                        ? *reinterpret_cast<const unsigned*>(a.r + (((long)b * a.H + yi) * a.W + xi) * 2)
+                        : 0u;
+        }
+    };
+    GemmArgs g{};   // the epilogue's view of the output
+    g.Ho = a.H;
+    g.Wo = a.W;
+    g.N = 32;
+    g.bmap = a.bmap;
+    g.relu = 1;
+    g.out = a.out;
+    rload(t);
+    unsigned long long work = 0;
+    typedef __bf16 bf16x2f __attribute__((ext_vector_type(2)));
+    while (true) {
+        int b, ty0, tx0;
+        origin(t, b, ty0, tx0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (tid + q * 256 < RP * RP) Rs[tid + q * 256] = rr[q];
+        __syncthreads();
+        const int tn = next_tile(t + gridDim.x);
+        if (tn < ntiles) rload(tn);
+        // h0 on the 18 x 18 patch at image origin (ty0 - 1, tx0 - 1), 16 pixels per MFMA step
+        for (int grp = wave; grp < (HP * HP + 15) / 16; grp += 4) {
+            const int p = grp * 16 + (lane & 15);
+            const int pc = p < HP * HP ? p : HP * HP - 1;
+            const int py = pc / HP, px = pc - py * HP;
+            bf16x8 fx = zero8();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int tap = kg * 4 + q;
+                if (tap >= 9) break;
+                const bf16x2f v2 = __builtin_bit_cast(bf16x2f, Rs[(py + tap / 3) * RP + px + tap % 3]);
+                fx[2 * q] = v2[0];
+                fx[2 * q + 1] = v2[1];
+            }
+            const int yi = ty0 - 1 + py, xi = tx0 - 1 + px;
+            const bool in = p < HP * HP && yi >= 0 && yi < a.H && xi >= 0 && xi < a.W;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j], fx, (f32x4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                bf16x4 o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = acc[e] + b0v[j][e];
+                    o[e] = (bf16)(in && v > 0.f ? v : 0.f);
+                }
+                if (p < HP * HP) *reinterpret_cast<bf16x4*>(&Ps[p][j * 16 + kg * 4]) = o;
+            }
+        }
+        __syncthreads();
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        halo_mma<32, 0>(Ps, Ws, 0, acc, lane, wave);
+        __syncthreads();
+        if (wc) {
+            const int my = a.H - ty0 < HT ? a.H - ty0 : HT, mx = a.W - tx0 < HT ? a.W - tx0 : HT;
+            work += (unsigned long long)my * mx * (2ull * 18 * 32 + 2ull * 288 * 32);
+        }
+        halo_epilogue_lds<32>(g, acc, b, ty0, tx0, 0, tid, &Ps[0][0], nullptr);
+        if (tn >= ntiles) break;
+        t = tn;
+    }
+    if (wc && tid == 0) work_atomic(wc, work);
+}
+
+int launch_first_ctx(const FirstCtxArgs& a, hipStream_t s) {
+    if (a.B <= 0 || a.H <= 0 || a.W <= 0) return HELM_OK;
+    if (a.K0 < 32 || a.Kh < 288) return fail(HELM_EINVAL, "first_ctx: weight depths %d, %d below 32, 288", a.K0, a.Kh);
+    if ((long)a.B * a.H * a.W >= (1L << 31) / 32) return fail(HELM_EINVAL, "first_ctx: grid too large");
+    static int res = 0;
+    const int tiles = ((a.H + HT - 1) / HT) * ((a.W + HT - 1) / HT) * a.B;
+    const int gx = std::max(1, std::min(tiles, resident_blocks(k_first_ctx, res)));
+    TIMED_LAUNCH("k_conv", s, k_first_ctx, dim3(gx), dim3(256), 0, s, a, WORK_COUNTER("k_conv", s));
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
+}
+
 int launch_resblock32(const ResArgs& a, hipStream_t s) {
     if (a.B <= 0 || a.H <= 0 || a.W <= 0) return HELM_OK;
     if (a.K1 < 288 || a.K2 < 288) return fail(HELM_EINVAL, "resblock32: weight depth below 9 x 32");
