@@ -239,8 +239,8 @@ int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsr
 /*
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
- * times every applicable kernel (halo-tiled persistent / one tile per block,
- * 32 or 64 output channels per block, implicit GEMM with 64x64, 128x32,
+ * times every applicable kernel (halo-tiled persistent with 16 or 32 output
+ * channels / one tile per block with 32 or 64, implicit GEMM with 64x64, 128x32,
  * 64x128 or 128x64 tiles, the direct first-layer kernel) on the caller's
  * buffers and keeps the fastest for that shape for the rest of the process;
  * launches inside a stream capture use the built-in rule until the shape has

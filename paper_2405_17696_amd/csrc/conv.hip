@@ -1378,7 +1378,8 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // buffers and keeps the fastest for that shape.  Only overwriting epilogues are
 // tuned (accumulating ones would add each candidate's result).
 enum ConvKernel {
-    CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W, CK_COUNT
+    CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W,
+    CK_PERS16, CK_COUNT
 };
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
@@ -1392,6 +1393,7 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_GEMM128: return true;
         case CK_GEMM64W: return a.N >= 128;
         case CK_GEMM128W: return a.N >= 64;
+        case CK_PERS16: return halo && a.N <= 16 && C == HC;   // narrow outputs (the 2-channel head)
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1416,6 +1418,8 @@ static void launch_halo_ck(const GemmArgs& a, hipStream_t s, unsigned long long*
             launch_pers<32, FLIP, EPI, 1>(a, s, wc);
         else
             launch_pers<32, FLIP, EPI, 2>(a, s, wc);
+    } else if (ck == CK_PERS16) {
+        launch_pers<16, FLIP, EPI, 1>(a, s, wc);
     } else if (ck == CK_HALO32) {
         launch_single<32, FLIP, EPI>(a, s, wc);
     } else {
@@ -1426,6 +1430,7 @@ static void launch_halo_ck(const GemmArgs& a, hipStream_t s, unsigned long long*
 static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long long* wc) {
     switch (ck) {
         case CK_PERS:
+        case CK_PERS16:
         case CK_HALO32:
         case CK_HALO64:
             if (a.gmode == G_CONVT)
