@@ -65,8 +65,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the graph-replay and MG comparison runs")
     ap.add_argument("--kernel", default=None, help="kernel whose roofline is reported")
     ap.add_argument("--sample-every", type=int, default=8,
-                    help="time and count every n-th launch of that kernel (event packets between all launches "
-                         "slow the timed solve by ~7%%)")
+                    help="time and count one launch in n of that kernel, chosen by a hash of the launch index "
+                         "(event packets between all launches slow the timed solve by ~7%%)")
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
@@ -94,7 +94,8 @@ def measured_traffic():
 
 def kernel_roofline(api_lib, name, every):
     """Average event-timed duration and algorithmic work of the sampled launches
-    (every every-th launch of the family in the timed region)."""
+    (one in every launches of the family in the timed region, by a hash of the
+    launch index)."""
     import ctypes as C
     n = C.c_int()
     ms = C.c_double()

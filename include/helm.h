@@ -268,10 +268,11 @@ int helm_conv_force(int kernel, int* kernel_count);
  * the algorithmic bytes (or flops) their active blocks processed.  Launches
  * recorded into a stream capture are neither timed nor counted (a replayed
  * graph has no per-launch events).  kernel = NULL stops timing.
- * helm_ktimer_sample(every) samples only every every-th launch of the family
- * (from the first after helm_ktimer_start; default 1 = all), which keeps the
- * event packets from slowing a long run; time and work are then both taken
- * over the sampled launches.  helm_ktimer_read synchronises the device and
+ * helm_ktimer_sample(every) samples on average one launch in every of the
+ * family (the first after helm_ktimer_start, then by a fixed hash of the launch
+ * index, so that no layer of a repeated sequence is favoured; default 1 = all),
+ * which keeps the event packets from slowing a long run; time and work are then
+ * both taken over the sampled launches.  helm_ktimer_read synchronises the device and
  * returns the sampled launches, their total event time and their total work
  * since the last start (host outputs).
  */

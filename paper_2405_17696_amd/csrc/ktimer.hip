@@ -55,10 +55,15 @@ void KTimer::end(hipStream_t s) {
     if (e && hipEventRecord(e, s) == hipSuccess) g_t.ev.push_back({g_t.pending, e});
     g_t.pending = nullptr;
 }
+// A launch is sampled when a multiplicative hash of its index falls in the
+// lowest 1/period of the 32-bit range: on average every period-th launch, but
+// not in step with the number of launches per network application (a fixed
+// stride would sample the same few layers whenever the two share a factor).
 void KTimer::next(const char* name, hipStream_t s) {
     if (!named(name) || stream_capturing(s)) return;
     ++g_t.launches;
-    g_t.sample = g_t.launches % g_t.period == 0;
+    const unsigned h = (unsigned)g_t.launches * 2654435761u;
+    g_t.sample = g_t.period <= 1 || h < 0xFFFFFFFFu / (unsigned)g_t.period;
 }
 void KTimer::replayed() {}
 void KTimer::harvest() {}
