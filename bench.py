@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=10, help="FGMRES cycle length of the CNN preconditioners")
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rhs", type=int, default=1)
+    ap.add_argument("--cpu-sample-rhs", type=int, default=4, help="RHS the oracle solves for cpu_baseline (~3 s each)")
     ap.add_argument("--net", default=None, help="trained network file for the CNN preconditioner")
     ap.add_argument("--save-net", default=None, help="write the trained network to this file")
     ap.add_argument("--no-compare", action="store_true", help="skip the graph-replay and MG comparison runs")
