@@ -150,7 +150,8 @@ def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=
     """Adam on fresh eq. (4.3) pairs in rounds of 500 steps (lr0 for 1000 steps,
     lr0/2 up to 3000, lr0/4 after).  Every eval_every steps the network is
     scored by the mean CNN-FGMRES iteration count on 8 validation sources (row
-    24, not the workload's row-4 sources) and the best-scoring weights are kept:
+    24, not the workload's row-4 sources); the best-scoring of the best
+    checkpoint and the averages of the best two and three checkpoints is kept:
     the training loss is a poor proxy for the preconditioner's quality.
     Training runs with the built-in kernel choice (autotuning off), so that the
     trained network, and with it the iteration count, does not depend on which
@@ -165,8 +166,12 @@ def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=
     vb = torch.tensor(vsrc, dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    def validate():
+        _, it, _, _, _ = api.helm_solve(op_t, vb, tol=1e-6, precond="cnn_vu", maxit=1000, net=net, restart=restart)
+        return float(it.mean())
+
     done, rnd, hist = 0, 0, []
-    best, best_step, best_theta, scores = None, 0, None, []
+    top, scores = [], []          # the three best checkpoints: (score, step, weights)
     while done < steps:
         chunk = min(500, steps - done)
         lr = lr0 if done < 1000 else (lr0 / 2 if done < 3000 else lr0 / 4)
@@ -176,11 +181,21 @@ def train_on(api, net, k2, gam, med, steps, lr0, restart, seed0=100, eval_every=
         done += chunk
         rnd += 1
         if done % eval_every == 0 or done == steps:
-            _, it, _, _, _ = api.helm_solve(op_t, vb, tol=1e-6, precond="cnn_vu", maxit=1000, net=net, restart=restart)
-            score = float(it.mean())
+            score = validate()
             scores.append([done, score])
-            if best is None or score < best:
-                best, best_step, best_theta = score, done, api.cnn_get_params(net)
+            top = sorted(top + [(score, done, api.cnn_get_params(net))], key=lambda c: c[0])[:3]
+    # candidates: the best checkpoint and the averages of the best two and three
+    # (checkpoint averaging), chosen by the same validation score
+    best, best_step, best_theta = top[0]
+    for k in (2, 3):
+        if len(top) < k:
+            continue
+        theta = (sum(c[2].astype(np.float64) for c in top[:k]) / k).astype(np.float32)
+        api.cnn_set_params(net, theta)
+        score = validate()
+        scores.append([f"mean of best {k}", score])
+        if score < best:
+            best, best_step, best_theta = score, f"mean of steps {sorted(c[1] for c in top[:k])}", theta
     api.cnn_set_params(net, best_theta)
     torch.cuda.synchronize()
     tt = time.perf_counter() - t0
