@@ -450,7 +450,7 @@ def main_c5(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU (the library has no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
     if a.tune_file and os.path.exists(a.tune_file):
         from paper_2405_17696_amd import api
