@@ -47,7 +47,7 @@ def test_param_layout_matches_oracle(gpu):
         assert net.nparams == U.n_params(U.all_layers(widths, dr))
 
 
-@pytest.mark.parametrize("nz,nx", [(32, 32), (48, 64)])
+@pytest.mark.parametrize("nz,nx", [(32, 32), (48, 64), (40, 56)])
 def test_forward_parity(gpu, nz, nx):
     print(f"cnn forward {nz}x{nx}", flush=True)
     med = medium(nz, nx, seed=7)
@@ -61,10 +61,12 @@ def test_forward_parity(gpu, nz, nx):
     assert relerr(out, ref) <= 3e-2
 
 
-@pytest.mark.parametrize("nz,nx,B", [(32, 32, 1), (48, 80, 3)])
+@pytest.mark.parametrize("nz,nx,B", [(32, 32, 1), (48, 80, 3), (40, 56, 2)])
 def test_forward_parity_full_width(gpu, nz, nx, B):
-    """Default architecture (32-256, two residual blocks per encoder level); the
-    48 x 80 case spans several 16 x 16 tiles with ragged edges on every level."""
+    """Default architecture (32-256, two residual blocks per encoder level), on
+    the inference path (fused first layer and residual blocks).  48 x 80 spans
+    several 16 x 16 tiles and leaves ragged 14 x 14 residual-block tiles; 40 x 56
+    leaves ragged 16 x 16 tiles on every level (40 x 56 down to 5 x 7)."""
     widths = (32, 64, 128, 256)
     med = medium(nz, nx, seed=9)
     H = setup(med)
