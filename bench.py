@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--restart", type=int, default=10, help="FGMRES cycle length of the CNN preconditioners")
     ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--mg-restart", type=int, default=20, help="GMRES cycle length of the c3 MG-GMRES solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rhs", type=int, default=4, help="RHS the oracle solves for cpu_baseline (~3 s each)")
     ap.add_argument("--net", default=None, help="trained network file for the CNN preconditioner")
@@ -339,7 +340,7 @@ def main_c3(a):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, it, rr, st, code = api.helm_solve(ops, b, tol=1e-6, rhs_op=rhs_op, precond="mg", maxit=a.maxit,
-                                             restart=20, use_graph=use_graph)
+                                             restart=a.mg_restart, use_graph=use_graph)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         conv = int((st == 0).sum())
@@ -354,7 +355,7 @@ def main_c3(a):
                                                  "converged_rhs_per_s": conv / dt, "groups": groups}
         print(f"c3 {'graph' if use_graph else 'eager'} done in {dt:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps({"workload": "c3 uneven batch: 256x512, 384x768, 512x1024 x 5/8/12 ppw x "
-                                  f"{nsrc} sources, MG-GMRES(20), tol 1e-6, maxit {a.maxit}",
+                                  f"{nsrc} sources, MG-GMRES({a.mg_restart}), tol 1e-6, maxit {a.maxit}",
                       "systems": len(rhs_op), "node_rhs": int(b.numel()), "results": res}))
 
 
