@@ -368,11 +368,12 @@ def main_c4(a):
     b = torch.tensor(src, dtype=torch.complex64, device="cuda")
     net, training = get_net(api, a, t(med2.kappa2), t(med2.gamma), med2)
 
-    def iters(pc, m):
+    def iters(pc, m, with_net=None):
         op = api.helm_setup(t(m.kappa2), t(m.gamma), m.omega, m.h)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, it, rr, st, code = api.helm_solve(op, b, tol=1e-6, precond=pc, maxit=a.maxit, net=net,
+        _, it, rr, st, code = api.helm_solve(op, b, tol=1e-6, precond=pc, maxit=a.maxit,
+                                             net=with_net if with_net is not None else net,
                                              restart=a.restart if pc != "mg" else 20)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -400,11 +401,61 @@ def main_c4(a):
         variants[name] = {"retraining_seconds": tr, "steps": len(hist), "dataset": dsz,
                           "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:])),
                           "after": iters("cnn_vu", med4)}
+    for lr in (1e-4, 2.5e-5, 1e-5):
+        variants[f"plain_selected_lr{lr:g}"] = retrain_selected(api, pre, op4, med4, iters, a, lr=lr)
     op4.close()
     mg = iters("mg", med4)
     print(json.dumps({"workload": "c4 retraining on the 5%-perturbed c2 medium: batch 16, 200 Adam steps, lr 1e-4; "
-                                  "plain = 2000 eq. (4.3) pairs, alg2 = Alg. 2 from 128 pairs, 3 data epochs",
+                                  "plain = 2000 eq. (4.3) pairs, alg2 = Alg. 2 from 128 pairs, 3 data epochs, "
+                                  "plain_selected_lr* = plain at that learning rate with the weights scored every 25 steps "
+                                  "on validation sources and the best kept (the pre-retraining weights included)",
                       "pretraining": training, "before": before, "retraining": variants, "mg": mg}))
+
+
+def retrain_selected(api, pre, op4, med4, iters, a, steps=200, every=25, npairs=2000, batch=16, lr=1e-4,
+                     seed=4001):
+    """The plain retraining (fixed set of eq. (4.3) pairs, Adam) with the
+    selection the pre-training uses: the weights are scored by the mean
+    CNN-FGMRES iteration count on 8 validation sources (row 24, not the
+    workload's row-4 sources) before training and every `every` steps, and the
+    best-scoring weights are kept.  Batches are random contiguous windows of
+    the pair set (the pairs are independent draws)."""
+    import torch
+    from paper_2405_17696_amd import synth
+    n = med4.kappa2.shape[0]
+    vb = torch.tensor(synth.point_sources(n, n, synth.surface_positions(n, 8), row=24, h=med4.h),
+                      dtype=torch.complex64, device="cuda")
+    net = api.cnn_load(pre)
+    api.helm_autotune(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def score():
+        _, it, _, _, _ = api.helm_solve(op4, vb, tol=1e-6, precond="cnn_vu", maxit=a.maxit, net=net,
+                                        restart=a.restart)
+        return float(it.mean())
+
+    r, e = api.cnn_make_pairs(op4, 0, npairs, seed)
+    rng = np.random.default_rng(seed)
+    scores = [[0, score()]]
+    best = (scores[0][1], 0, api.cnn_get_params(net))
+    losses = []
+    for step in range(1, steps + 1):
+        s0 = int(rng.integers(0, npairs - batch + 1))
+        losses.append(api.cnn_loss_grad(net, op4, r[s0:s0 + batch], e[s0:s0 + batch]))
+        api.cnn_adam_step(net, lr)
+        if step % every == 0:
+            v = score()
+            scores.append([step, v])
+            if v < best[0]:
+                best = (v, step, api.cnn_get_params(net))
+    api.cnn_set_params(net, best[2])
+    torch.cuda.synchronize()
+    tr = time.perf_counter() - t0
+    api.helm_autotune(1)
+    out = {"retraining_seconds": tr, "steps": steps, "dataset": npairs, "loss_first": float(losses[0]),
+           "loss_last20": float(np.mean(losses[-20:])), "validation_iters": scores, "selected_step": best[1]}
+    return out | {"after": iters("cnn_vu", med4, net)}
 
 
 def main_c5(a):
