@@ -5,6 +5,12 @@ oracle can compute one by one and on properties that hold at any size.
   workload): CNN-FGMRES(10) with M_VU and MG-GMRES(20); every returned solution's
   FP64 residual is recomputed by the oracle's operator, and sampled right-hand
   sides are compared with the oracle's sparse direct solve.
+* the uneven batch at its full size: 576 systems (256 x 512, 384 x 768 and
+  512 x 1024 grids, 5/8/12 points per wavelength, 64 sources) in one masked
+  MG-GMRES(20) launch as the bench times it (maxit 2000): every
+  returned residual is recomputed by the oracle's operator, systems that stop
+  at maxit report status 1, and one sampled system per grid and frequency
+  equals its own single-system solve bit for bit;
 * 512 x 512 FWI setting (four frequencies, 128 receivers on row 4): the misfit
   gradient against the oracle's adjoint-state gradient, with two of the 128
   sources (the oracle factorises each frequency once).
@@ -69,3 +75,40 @@ def test_fwi_gradient_full_grid(gpu):
     assert code == 0
     assert abs(phi - phi_o) <= 1e-2 * phi_o
     assert relerr(g.cpu().numpy().astype(np.float64), g_o) <= 1e-3
+
+
+def test_uneven_batch_full_size(gpu):
+    items = synth.config3_media(nsrc=64)
+    ops, parts, rhs_op, meds = [], [], [], []
+    for k, (med, src) in enumerate(items):
+        k2 = torch.tensor(med.kappa2, dtype=torch.float32, device="cuda")
+        g = torch.tensor(med.gamma, dtype=torch.float32, device="cuda")
+        ops.append(api.helm_setup(k2, g, med.omega, med.h))
+        parts.append(src.reshape(src.shape[0], -1))
+        rhs_op += [k] * src.shape[0]
+        meds.append(med)
+    b = torch.tensor(np.concatenate([q.ravel() for q in parts]), dtype=torch.complex64, device="cuda")
+    print("uneven batch full size:", len(rhs_op), "systems,", b.numel(), "node-RHS", flush=True)
+    maxit = 2000
+    x, it, rr, st, code = api.helm_solve(ops, b, tol=1e-6, rhs_op=rhs_op, precond="mg", maxit=maxit, restart=20)
+    conv = st == 0
+    assert len(rhs_op) == 576 and code in (0, 1) and conv.any()
+    assert np.all(rr[conv] <= 1e-6)
+    assert np.all(st[~conv] == 1) and np.all(it[~conv] == maxit)
+    offs = np.concatenate([[0], np.cumsum([ops[k].n for k in rhs_op])])
+    xh = x.cpu().numpy()
+    for k, med in enumerate(meds):
+        nz, nx = med.kappa2.shape
+        coef = op.helmholtz_coef(f32(med.kappa2), f32(med.gamma), med.omega)
+        sel = [i for i, o in enumerate(rhs_op) if o == k]
+        for j, i in enumerate(sel):
+            xi = xh[offs[i]:offs[i + 1]].reshape(1, nz, nx)
+            bi = parts[k][j].astype(np.complex64).astype(np.complex128).reshape(1, nz, nx)
+            r = op.relres(coef, xi, bi, med.h, med.h)[0]
+            assert abs(r - rr[i]) <= 1e-6 * max(r, 1e-12) + 1e-12, (k, j, r, rr[i])
+        i = sel[0]
+        xs, its, rrs, sts, _ = api.helm_solve(ops[k], b[offs[i]:offs[i + 1]], tol=1e-6, precond="mg",
+                                              maxit=maxit, restart=20)
+        print("grid", (nz, nx), "omega", round(med.omega, 3), "system", i, "its", int(its[0]), flush=True)
+        assert its[0] == it[i] and sts[0] == st[i] and rrs[0] == rr[i]
+        assert torch.equal(xs, x[offs[i]:offs[i + 1]])
