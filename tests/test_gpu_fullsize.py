@@ -11,6 +11,10 @@ oracle can compute one by one and on properties that hold at any size.
   returned residual is recomputed by the oracle's operator, systems that stop
   at maxit report status 1, and one sampled system per grid and frequency
   equals its own single-system solve bit for bit;
+* the retraining data at its full size: 2000 eq. (4.3) pairs on the 256 x 256
+  perturbed medium in one call (seed of the bench's retraining); H e = r on
+  pairs sampled across the set, and two of them against the oracle's own pair
+  generation for the same sample indices;
 * 512 x 512 FWI setting (four frequencies, 128 receivers on row 4): the misfit
   gradient against the oracle's adjoint-state gradient, with two of the 128
   sources (the oracle factorises each frequency once).
@@ -22,6 +26,8 @@ import torch
 from helpers import f32, relerr
 from oracle import fwi
 from oracle import operator as op
+from oracle import multigrid as mg
+from oracle import train as T
 from paper_2405_17696_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -112,3 +118,24 @@ def test_uneven_batch_full_size(gpu):
         print("grid", (nz, nx), "omega", round(med.omega, 3), "system", i, "its", int(its[0]), flush=True)
         assert its[0] == it[i] and sts[0] == st[i] and rrs[0] == rr[i]
         assert torch.equal(xs, x[offs[i]:offs[i + 1]])
+
+
+def test_retraining_pairs_full_size(gpu):
+    med = synth.config4_medium()
+    k2, gam = f32(med.kappa2), f32(med.gamma)
+    H = api.helm_setup(torch.tensor(k2, device="cuda"), torch.tensor(gam, device="cuda"), med.omega, med.h)
+    npairs, seed = 2000, 4001
+    print("retraining pairs full size", npairs, flush=True)
+    r, e = api.cnn_make_pairs(H, first=0, npairs=npairs, seed=seed)
+    coef = op.helmholtz_coef(k2, gam, med.omega)
+    idx = [0, 1, 613, 1024, 1999]
+    rs = r[idx].cpu().numpy().astype(np.complex128)
+    es = e[idx].cpu().numpy().astype(np.complex128)
+    for t in range(len(idx)):
+        assert np.all(np.isfinite(rs[t])) and relerr(op.apply(coef, es[t], med.h, med.h), rs[t]) <= 1e-5
+    V = mg.VCycle(k2, gam, med.omega, med.h)
+    n = k2.shape[0]
+    for t, i in ((1, 1), (4, 1999)):
+        R0, E0, ks = T.make_pairs(coef, med.h, med.h, V, (n, n), 1, seed=seed, first=i)
+        print("pair", i, "k", ks, "e rel", relerr(es[t], E0[0]), flush=True)
+        assert relerr(es[t], E0[0]) <= 2e-3 and relerr(rs[t], R0[0]) <= 2e-3
