@@ -80,6 +80,7 @@ int helm_op_info(helm_op_t op, int* nz, int* nx, double* omega, double* hx, doub
  * helm_matvec -- v = H u (adjoint = 0) or v = H^* u (adjoint = 1) for nrhs
  * vectors [nrhs][nz][nx] of type dtype (HELM_C64 or HELM_C128).  u and v must
  * not overlap.  Eq. (3.2); H^* = conj(H) because H is complex symmetric (Sec. 4.3).
+ * nrhs = 0 is a no-op (u and v may then be NULL).
  */
 int helm_matvec(helm_op_t op, const void* u, void* v, int nrhs, int dtype, int adjoint, void* stream);
 
@@ -100,14 +101,15 @@ typedef struct {
  * helm_solve -- flexible GMRES(m), right preconditioned, for a batch of
  * systems H_{op(r)} x_r = b_r (Sec. 3.4, eq. (3.14)).
  *   ops[nops]: operators; rhs_op[nrhs] (host): operator index of each RHS,
- *     non-decreasing (RHS grouped by operator);
+ *     non-decreasing (RHS grouped by operator); NULL puts every RHS on ops[0];
  *   rhs: c64 right-hand sides, back to back in RHS order (device);
  *   x:   c128 solutions, same layout (device; in: initial guess if x0_given);
  *   iters, relres, status [nrhs] (host outputs, may be NULL): iterations,
  *     FP64 ||b - H x|| / ||b||, and per-RHS HELM_OK / HELM_NOT_CONVERGED /
  *     HELM_ENAN.
  * Stopping: relres <= tol with the residual recomputed in FP64 from the c128
- * iterate at every restart; b = 0 gives x = 0.  Returns HELM_OK when every RHS
+ * iterate at every restart; b = 0 gives x = 0.  nrhs = 0 is a no-op that
+ * returns HELM_OK (rhs and x may then be NULL).  Returns HELM_OK when every RHS
  * converged, HELM_NOT_CONVERGED otherwise, or a hard error.
  */
 int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* x, int nrhs,
@@ -116,7 +118,8 @@ int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rh
 
 /*
  * helm_vcycle -- e = V_SL(f): one shifted-Laplacian V-cycle from e = 0
- * (Sec. 3.4, "levels = 3") for nrhs c64 vectors (device).  Linear in f.
+ * (Sec. 3.4, three levels) for nrhs c64 vectors (device).  Linear in f.
+ * nrhs = 0 is a no-op (f and e may then be NULL).
  */
 int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
 /* Roots of the coarsest-level polynomial, in application order (host, c128 [*n]). */

@@ -467,8 +467,9 @@ int helm_op_info(helm_op_t op, int* nz, int* nx, double* omega, double* hx, doub
 }
 
 int helm_matvec(helm_op_t op, const void* u, void* v, int nrhs, int dtype, int adjoint, void* stream) {
-    if (!op || !u || !v || nrhs < 0) return fail(HELM_EINVAL, "helm_matvec: bad arguments");
-    if (nrhs == 0) return HELM_OK;
+    if (!op || nrhs < 0) return fail(HELM_EINVAL, "helm_matvec: bad arguments");
+    if (nrhs == 0) return HELM_OK;   // an empty batch: the buffers may be NULL
+    if (!u || !v) return fail(HELM_EINVAL, "helm_matvec: NULL buffer");
     hipStream_t s = (hipStream_t)stream;
     if (dtype == HELM_C64) return launch_matvec<float>(op, (const c64*)u, (c64*)v, nrhs, adjoint, s);
     if (dtype == HELM_C128) return launch_matvec<double>(op, (const c128*)u, (c128*)v, nrhs, adjoint, s);
@@ -476,8 +477,9 @@ int helm_matvec(helm_op_t op, const void* u, void* v, int nrhs, int dtype, int a
 }
 
 int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream) {
-    if (!op || !f || !e || nrhs < 0) return fail(HELM_EINVAL, "helm_vcycle: bad arguments");
-    if (nrhs == 0) return HELM_OK;
+    if (!op || nrhs < 0) return fail(HELM_EINVAL, "helm_vcycle: bad arguments");
+    if (nrhs == 0) return HELM_OK;   // an empty batch: the buffers may be NULL
+    if (!f || !e) return fail(HELM_EINVAL, "helm_vcycle: NULL buffer");
     std::lock_guard<std::mutex> lk(g_mutex);
     hipStream_t s = (hipStream_t)stream;
     SolveWork& W = g_work;
@@ -513,8 +515,9 @@ int helm_coarse_roots(helm_op_t op, double* roots, int* n) {
 
 int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* x, int nrhs, double tol,
                const helm_solve_opts* opt, int* iters, double* relres, int* status, void* stream) {
-    if (!ops || nops <= 0 || !rhs || !x || nrhs < 0) return fail(HELM_EINVAL, "helm_solve: bad arguments");
-    if (nrhs == 0) return HELM_OK;
+    if (!ops || nops <= 0 || nrhs < 0) return fail(HELM_EINVAL, "helm_solve: bad arguments");
+    if (nrhs == 0) return HELM_OK;   // an empty batch: the buffers may be NULL
+    if (!rhs || !x) return fail(HELM_EINVAL, "helm_solve: NULL buffer");
     for (int i = 0; i < nops; ++i)
         if (!ops[i]) return fail(HELM_EINVAL, "helm_solve: ops[%d] is NULL", i);
     if (!(tol > 0)) return fail(HELM_EINVAL, "helm_solve: tol must be positive");

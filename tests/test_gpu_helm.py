@@ -9,6 +9,7 @@ from oracle import krylov as kr
 from oracle import multigrid as mg
 from oracle import operator as op
 from paper_2405_17696_amd import api, synth
+from paper_2405_17696_amd._lib import HelmError
 
 pytestmark = pytest.mark.gpu
 
@@ -124,6 +125,31 @@ def test_solve_batch_and_edges(gpu):
     bn[0, 3, 3] = np.nan
     x, it, rr, st, code = api.helm_solve(H, to_dev(bn), tol=1e-6, precond="mg")
     assert st[0] == -4 and st[1] == 0
+
+
+def test_empty_batch_and_argument_errors(gpu):
+    """nrhs = 0 is a no-op for the solve, the product and the V-cycle; bad
+    arguments come back as errors with the library's message."""
+    n = 32
+    med = medium(n, n, seed=3)
+    H = setup(med)
+    empty = torch.empty((0, n, n), dtype=torch.complex64, device="cuda")
+    x, it, rr, st, code = api.helm_solve(H, empty, tol=1e-6, precond="mg")
+    assert code == 0 and x.numel() == 0 and it.size == 0 and st.size == 0
+    assert api.helm_matvec(H, empty).numel() == 0
+    assert api.helm_vcycle(H, empty).numel() == 0
+    b = to_dev(rand_c((1, n, n), 2).astype(np.complex64))
+    with pytest.raises(HelmError, match="restart"):
+        api.helm_solve(H, b, precond="mg", restart=65)
+    with pytest.raises(HelmError, match="tol"):
+        api.helm_solve(H, b, tol=0.0, precond="mg")
+    with pytest.raises(HelmError, match="net"):
+        api.helm_solve(H, b, precond="cnn_vu")
+    with pytest.raises(ValueError):
+        api.helm_solve(H, b[:, :5], precond="mg")
+    # the operator still works after the rejected calls
+    x, it, rr, st, code = api.helm_solve(H, b, tol=1e-6, precond="mg")
+    assert code == 0 and st[0] == 0
 
 
 def test_solve_adjoint(gpu):
