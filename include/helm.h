@@ -155,7 +155,8 @@ int cnn_zero_grad(cnn_net_t net);
 /* Raw network: out = SolverNet(rin; EncoderNet(op)), rin and out FP32
  * [B][nz][nx][2] (device). */
 int cnn_forward(cnn_net_t net, helm_op_t op, const float* rin, float* out, int B, void* stream);
-/* e = M_net(r) = hx hz net(s r) / s for nrhs c64 vectors (device); Sec. 3.4. */
+/* e = M_net(r) = hx hz net(s r) / s for nrhs c64 vectors (device); Sec. 3.4.
+ * nrhs = 0 is a no-op (r and e may then be NULL). */
 int cnn_precond_apply(cnn_net_t net, helm_op_t op, const void* r, void* e, int nrhs, void* stream);
 /* MSE loss of eq. (4.2) on B pairs (r, e) (c64, device) and its gradient,
  * accumulated into the network's gradient buffer; loss to host (may be NULL). */

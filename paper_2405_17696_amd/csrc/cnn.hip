@@ -1718,8 +1718,9 @@ int cnn_layer_backward(int kind, int stride, int B, int H, int W, int c1, int c2
 }
 
 int cnn_precond_apply(cnn_net_t n, helm_op_t op, const void* r, void* e, int nrhs, void* stream) {
-    if (!n || !op || !r || !e || nrhs < 0) return fail(HELM_EINVAL, "cnn_precond_apply: bad arguments");
-    if (nrhs == 0) return HELM_OK;
+    if (!n || !op || nrhs < 0) return fail(HELM_EINVAL, "cnn_precond_apply: bad arguments");
+    if (nrhs == 0) return HELM_OK;   // an empty batch: the buffers may be NULL
+    if (!r || !e) return fail(HELM_EINVAL, "cnn_precond_apply: NULL buffer");
     std::lock_guard<std::recursive_mutex> lk(g_cnn_mutex);
     return apply_impl<float>(n, op, (const c64*)r, nullptr, 0, (c64*)e, nrhs, nullptr, 0, (hipStream_t)stream);
 }

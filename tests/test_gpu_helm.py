@@ -128,8 +128,8 @@ def test_solve_batch_and_edges(gpu):
 
 
 def test_empty_batch_and_argument_errors(gpu):
-    """nrhs = 0 is a no-op for the solve, the product and the V-cycle; bad
-    arguments come back as errors with the library's message."""
+    """nrhs = 0 is a no-op for the solve, the product, the V-cycle and the network
+    preconditioner; bad arguments come back as errors with the library's message."""
     n = 32
     med = medium(n, n, seed=3)
     H = setup(med)
@@ -138,6 +138,7 @@ def test_empty_batch_and_argument_errors(gpu):
     assert code == 0 and x.numel() == 0 and it.size == 0 and st.size == 0
     assert api.helm_matvec(H, empty).numel() == 0
     assert api.helm_vcycle(H, empty).numel() == 0
+    assert api.cnn_precond_apply(api.cnn_create(seed=1), H, empty).numel() == 0
     b = to_dev(rand_c((1, n, n), 2).astype(np.complex64))
     with pytest.raises(HelmError, match="restart"):
         api.helm_solve(H, b, precond="mg", restart=65)
