@@ -19,6 +19,16 @@ tests decide).  With the adjoint field
 the gradient is
     dPhi/dm_k = sum_{f,s} Re( conj(lambda_fs[k]) w_f^2 (1 - i gamma_k) u_fs[k] ).
 
+Simultaneous sources (Sec. 3.2, eq. 3.6-3.8): the sum over sources of a
+frequency's data term is a squared Frobenius norm, ||R H_f^{-1} G - D_f||_F^2
+with G = [g_1 .. g_ns] and D_f = [d_f1 .. d_fns], and the trace estimator with
+an ns x p matrix X of Rademacher columns replaces it by
+(1/p) ||R H_f^{-1} G X - D_f X||_F^2.  Every receiver here records every
+source, so the auxiliary data of eq. 3.7 are the observed data themselves.
+The encoded misfit and its gradient are those above with the p encoded
+sources G x_i and encoded data D_f x_i in place of the ns point sources, and a
+factor 1/p.
+
 All solves are SuperLU factorisations in complex128.
 """
 from __future__ import annotations
@@ -113,3 +123,30 @@ def born_adjoint(kappa2, gamma, omegas, hx, src_idx, rec_idx, dd, hz=None):
         lam = S.solve(q, trans="H")
         acc += np.sum(np.real(np.conj((w ** 2) * (1.0 - 1j * gam) * u) * lam), axis=0)
     return acc.reshape(nz, nx)
+
+
+def misfit_and_grad_encoded(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, X, hz=None):
+    """Phi_X = 1/2 (1/p) sum_f sum_i || R H_f^{-1} G x_i - D_f x_i ||^2 and its
+    gradient w.r.t. m (float64 [nz][nx]); X real [ns][p] (Rademacher in use,
+    any real matrix here), dobs [nf][ns][nrec]."""
+    hz = hx if hz is None else hz
+    nz, nx = kappa2.shape
+    n = nz * nx
+    X = np.asarray(X, np.float64)
+    p = X.shape[1]
+    rec = np.asarray(rec_idx)
+    G = point_source_rhs((nz, nx), src_idx, hx, hz).reshape(len(src_idx), n)   # rows g_s
+    q = X.T @ G                                          # encoded sources, [p][n]
+    phi = 0.0
+    grad = np.zeros(n)
+    gam = np.asarray(gamma, np.float64).ravel()
+    for f, (w, S) in enumerate(zip(omegas, _solvers(kappa2, gamma, omegas, hx, hz))):
+        u = S.solve(q)                                   # H_f^{-1} G x_i, [p][n]
+        dx = X.T @ np.asarray(dobs[f])                   # D_f x_i, [p][nrec]
+        res = u[:, rec] - dx
+        phi += 0.5 * float(np.sum(np.abs(res) ** 2)) / p
+        src_adj = np.zeros_like(u)
+        src_adj[:, rec] = res
+        lam = np.conj(S.solve(np.conj(src_adj)))
+        grad += np.sum(np.real(np.conj(lam) * (w ** 2) * (1.0 - 1j * gam) * u), axis=0) / p
+    return phi, grad.reshape(nz, nx)

@@ -1,6 +1,8 @@
 """Pins of the oracle's misfit gradient (eq. 3.5, 3.10, 4.8) against central
 finite differences of the misfit, a dot-product test between independently
-computed Born and adjoint-Born operators, and special cases (CPU only)."""
+computed Born and adjoint-Born operators, and special cases (CPU only).  The
+simultaneous-source misfit (eq. 3.6-3.8) is pinned by its identity-encoding
+case, by the exact average over all sign vectors, and by finite differences."""
 import numpy as np
 import pytest
 
@@ -92,3 +94,43 @@ def test_point_source_scaling():
     g = fwi.point_source_rhs((4, 5), [7], 0.5, 0.25)
     assert g.shape == (1, 4, 5)
     assert g[0, 1, 2] == 8.0 and np.count_nonzero(g) == 1
+
+
+def test_encoded_with_identity_is_unencoded_over_p():
+    # X = I (p = ns): the encoded sources are the point sources themselves
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    phi, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    p = len(src)
+    phx, gx = fwi.misfit_and_grad_encoded(k2, gamma, omegas, h, src, rec, dobs, np.eye(p))
+    assert abs(phx * p - phi) <= 1e-12 * phi
+    assert np.abs(gx * p - g).max() <= 1e-10 * np.abs(g).max()
+
+
+def test_encoded_average_over_all_sign_vectors_is_exact():
+    # with every one of the 2^ns sign vectors as a column, (1/p) X X^T = I
+    # exactly, so the trace estimator returns the misfit and gradient exactly
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    ns = len(src)
+    X = np.array([[1.0 if (j >> s) & 1 else -1.0 for j in range(2 ** ns)] for s in range(ns)])
+    assert np.allclose(X @ X.T / X.shape[1], np.eye(ns))
+    phi, g = fwi.misfit_and_grad(k2, gamma, omegas, h, src, rec, dobs)
+    phx, gx = fwi.misfit_and_grad_encoded(k2, gamma, omegas, h, src, rec, dobs, X)
+    assert abs(phx - phi) <= 1e-12 * phi
+    assert np.abs(gx - g).max() <= 1e-10 * np.abs(g).max()
+    # one sign vector alone is not the misfit: the estimator is random
+    ph1, _ = fwi.misfit_and_grad_encoded(k2, gamma, omegas, h, src, rec, dobs, X[:, :1])
+    assert abs(ph1 - phi) > 1e-6 * phi
+
+
+def test_encoded_gradient_central_differences():
+    k2, gamma, omegas, h, src, rec, dobs = small_problem()
+    X = np.where(np.random.default_rng(8).random((len(src), 2)) < 0.5, -1.0, 1.0)
+    _, g = fwi.misfit_and_grad_encoded(k2, gamma, omegas, h, src, rec, dobs, X)
+    rng = np.random.default_rng(12)
+    for t in range(3):
+        d = rng.standard_normal(k2.shape)
+        eps = 1e-3 * np.abs(k2).max() / np.abs(d).max()
+        fp = fwi.misfit_and_grad_encoded(k2 + eps * d, gamma, omegas, h, src, rec, dobs, X)[0]
+        fm = fwi.misfit_and_grad_encoded(k2 - eps * d, gamma, omegas, h, src, rec, dobs, X)[0]
+        fd = (fp - fm) / (2 * eps)
+        assert abs(np.sum(g * d) - fd) <= 1e-5 * abs(fd), (t, np.sum(g * d), fd)
