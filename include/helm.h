@@ -241,6 +241,28 @@ int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsr
                     int* iters, void* stream);
 
 /*
+ * fwi_misfit_grad_encoded -- the same misfit with simultaneous sources
+ * (Sec. 3.2, eq. (3.6)-(3.8)): for an nsrc x p matrix X (Rademacher columns in
+ * the method; any finite real matrix is accepted), the source sum of each
+ * frequency is replaced by its trace estimate
+ *   Phi_X = 1/2 (1/p) sum_f sum_i || R H_f^{-1} G x_i - D_f x_i ||^2,
+ * G x_i = sum_s X[s][i] g_s and D_f x_i = sum_s X[s][i] d_fs, and grad is dPhi_X/dm.
+ * Every receiver records every source, so the observed data are the data of the
+ * encoded sum (the auxiliary data of eq. (3.7) coincide with them).
+ *   X: float [nsrc][p] (host), drawn by the caller;
+ *   dobs: the unencoded observed data, c64 [nfreq][nsrc][nrec] (device);
+ *   iters (host, may be NULL): [2][nfreq][p];
+ *   the other arguments as for fwi_misfit_grad.
+ * nfreq * p forward and nfreq * p adjoint solves instead of nfreq * nsrc of
+ * each.  X = the nsrc x nsrc identity gives fwi_misfit_grad's misfit and
+ * gradient divided by nsrc.  Returns as fwi_misfit_grad; EINVAL for p <= 0 or a
+ * non-finite entry of X.
+ */
+int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const float* X, int p,
+                            const int* rec_idx, int nrec, const void* dobs, double tol, const helm_solve_opts* opt,
+                            double* misfit, float* grad, int* iters, void* stream);
+
+/*
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
  * times every applicable kernel (halo-tiled persistent with 16 or 32 output

@@ -87,6 +87,10 @@ SIGNATURES = {
     "fwi_misfit_grad": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
                                   C.POINTER(C.c_int), C.c_int, C.c_void_p, C.c_double, C.POINTER(SolveOpts),
                                   C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_int), C.c_void_p]),
+    "fwi_misfit_grad_encoded": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int,
+                                          C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_void_p,
+                                          C.c_double, C.POINTER(SolveOpts), C.POINTER(C.c_double), C.c_void_p,
+                                          C.POINTER(C.c_int), C.c_void_p]),
     "cnn_precond_train": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(TrainOpts), C.c_uint64,
                                     C.POINTER(C.c_float), C.c_void_p]),
     "cnn_layer_forward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 5 + [C.c_int, C.c_void_p]),

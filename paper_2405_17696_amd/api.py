@@ -366,6 +366,44 @@ def fwi_misfit_grad(ops, src_idx, rec_idx, dobs: torch.Tensor, tol: float = 1e-6
     return phi.value, grad, np.array(its[:], dtype=np.int64).reshape(2, nf, ns), code
 
 
+def fwi_misfit_grad_encoded(ops, src_idx, X, rec_idx, dobs: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
+                            restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
+                            reorth: bool = False, net=None, grad: torch.Tensor | None = None):
+    """Simultaneous-source misfit 1/2 (1/p) sum |R H^{-1} G x_i - D x_i|^2 and its
+    gradient (Sec. 3.2); X real [nsrc][p] (host), dobs the unencoded data,
+    complex64 [nfreq][nsrc][nrec] on the GPU.  Returns (misfit, grad float32
+    [nz][nx], iters [2][nfreq][p], code)."""
+    import numpy as np
+    lib = L.load()
+    if isinstance(ops, HelmOp):
+        ops = [ops]
+    src = [int(v) for v in np.asarray(src_idx).ravel()]
+    rec = [int(v) for v in np.asarray(rec_idx).ravel()]
+    nf, ns, nr = len(ops), len(src), len(rec)
+    Xh = np.ascontiguousarray(np.asarray(X, dtype=np.float32))
+    if Xh.ndim != 2 or Xh.shape[0] != ns:
+        raise ValueError(f"X must be [nsrc={ns}][p]")
+    p = Xh.shape[1]
+    if dobs.dtype != torch.complex64 or tuple(dobs.shape) != (nf, ns, nr):
+        raise ValueError(f"dobs must be complex64 of shape {(nf, ns, nr)}")
+    dobs = dobs.contiguous()
+    if grad is None:
+        grad = torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=dobs.device)
+    if grad.dtype != torch.float32 or grad.numel() != ops[0].n:
+        raise ValueError("grad must be float32 [nz][nx]")
+    handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
+                    L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+    phi = C.c_double()
+    its = (C.c_int * (2 * nf * p))()
+    code = lib.fwi_misfit_grad_encoded(handles, nf, (C.c_int * ns)(*src), ns,
+                                       Xh.ctypes.data_as(C.POINTER(C.c_float)), p, (C.c_int * nr)(*rec), nr,
+                                       _ptr(dobs), float(tol), C.byref(o), C.byref(phi), _ptr(grad), its, _stream())
+    L.check(code, soft_ok=True)
+    return phi.value, grad, np.array(its[:], dtype=np.int64).reshape(2, nf, p), code
+
+
 class FwiMisfit(torch.autograd.Function):
     """Phi(m) = 1/2 sum_{f,s} |R H_f(m)^{-1} g_s - d_fs|^2 as a differentiable function
     of the squared slowness m (float32 [nz][nx] on the GPU).  The forward pass runs

@@ -12,7 +12,14 @@
 //
 // The last line follows from dH_f/dm_k = -w_f^2 (1 - i gamma_k) e_k e_k^T
 // (eq. 3.1); the Jacobian printed with eq. (3.10) carries the opposite sign.
+//
+// Simultaneous sources (Sec. 3.2, eq. 3.6-3.8): with an ns x p matrix X of
+// Rademacher columns (drawn by the caller), the frequency's source sum is
+// replaced by the trace estimate (1/p) sum_i || R H_f^{-1} G x_i - D_f x_i ||^2:
+// p encoded sources G x_i and encoded data D_f x_i take the place of the ns
+// point sources and their data, and misfit and gradient carry the factor 1/p.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -26,6 +33,41 @@ __global__ void k_point_sources(const int* __restrict__ src, int ns, int nfs, lo
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nfs) return;
     rhs[(long)t * N + src[t % ns]] = c64{amp, 0.f};
+}
+
+// Encoded sources into the zeroed rhs: rhs_(f,i) = amp sum_s X[s][i] e_src(s),
+// one thread per (f, i) adding the sources in order (coinciding source nodes
+// add up).
+__global__ void k_encoded_sources(const int* __restrict__ src, const float* __restrict__ X, int ns, int p, int nfp,
+                                  long N, float amp, c64* __restrict__ rhs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nfp) return;
+    const int i = t % p;
+    c64* r = rhs + (long)t * N;
+    for (int s = 0; s < ns; ++s) {
+        c64 v = r[src[s]];
+        v.re += amp * X[(long)s * p + i];
+        r[src[s]] = v;
+    }
+}
+
+// Encoded data dx[f][i][r] = sum_s X[s][i] dobs[f][s][r], summed in FP64 in
+// source order and stored as c64.
+__global__ void k_encode_data(const c64* __restrict__ dobs, const float* __restrict__ X, int ns, int p, int nrec,
+                              long total, c64* __restrict__ dx) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int r = (int)(t % nrec);
+    const long fi = t / nrec;
+    const int i = (int)(fi % p), f = (int)(fi / p);
+    double re = 0, im = 0;
+    for (int s = 0; s < ns; ++s) {
+        const c64 d = dobs[((long)f * ns + s) * nrec + r];
+        const double w = X[(long)s * p + i];
+        re += w * d.re;
+        im += w * d.im;
+    }
+    dx[t] = c64{(float)re, (float)im};
 }
 
 // One block per (f, s): residual at the receivers (FP64), the adjoint source
@@ -86,63 +128,46 @@ struct Owned {
     }
 };
 
-}  // namespace
-}  // namespace helm
-
-using namespace helm;
-
-extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
-                               int nrec, const void* dobs, double tol, const helm_solve_opts* opt, double* misfit,
-                               float* grad, int* iters, void* stream) {
-    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit || !grad)
-        return fail(HELM_EINVAL, "fwi_misfit_grad: bad arguments");
-    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad: tol must be positive");
+// Checks shared by both entry points.
+static int check_args(const char* name, const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
+                      const int* rec_idx, int nrec) {
     for (int f = 0; f < nfreq; ++f) {
-        if (!ops[f]) return fail(HELM_EINVAL, "fwi_misfit_grad: ops[%d] is NULL", f);
+        if (!ops[f]) return fail(HELM_EINVAL, "%s: ops[%d] is NULL", name, f);
         const helm_op* a = ops[f];
         const helm_op* b = ops[0];
         if (a->nz != b->nz || a->nx != b->nx || a->hx != b->hx || a->hz != b->hz)
-            return fail(HELM_EINVAL, "fwi_misfit_grad: operator %d is on a different grid", f);
+            return fail(HELM_EINVAL, "%s: operator %d is on a different grid", name, f);
     }
     const long N = ops[0]->n();
     for (int i = 0; i < nsrc; ++i)
-        if (src_idx[i] < 0 || src_idx[i] >= N) return fail(HELM_EINVAL, "fwi_misfit_grad: source %d out of range", i);
+        if (src_idx[i] < 0 || src_idx[i] >= N) return fail(HELM_EINVAL, "%s: source %d out of range", name, i);
     std::vector<int> rs(rec_idx, rec_idx + nrec);
     std::sort(rs.begin(), rs.end());
     for (int i = 0; i < nrec; ++i) {
-        if (rs[i] < 0 || rs[i] >= N) return fail(HELM_EINVAL, "fwi_misfit_grad: receiver index out of range");
-        if (i && rs[i] == rs[i - 1]) return fail(HELM_EINVAL, "fwi_misfit_grad: receiver nodes must be distinct");
+        if (rs[i] < 0 || rs[i] >= N) return fail(HELM_EINVAL, "%s: receiver index out of range", name);
+        if (i && rs[i] == rs[i - 1]) return fail(HELM_EINVAL, "%s: receiver nodes must be distinct", name);
     }
-    helm_solve_opts o;
-    memset(&o, 0, sizeof(o));
-    if (opt) o = *opt;
-    if (o.adjoint) return fail(HELM_EINVAL, "fwi_misfit_grad: opts.adjoint must be 0 (the call runs both solves)");
-    o.x0_given = 0;
+    return HELM_OK;
+}
 
-    hipStream_t s = (hipStream_t)stream;
-    const int nfs = nfreq * nsrc;
-    Owned own;
-    c64* rhs = own.get<c64>((size_t)nfs * N);
+// From nper prepared right-hand sides per frequency (rhs, zero outside the
+// sources) and their data dobs_d [nfreq][nper][nrec] (device): forward solves,
+// residuals and misfit, adjoint solves, gradient; misfit and gradient times scale.
+static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs, const c64* dobs_d,
+                            const int* rec_d, int nrec, double tol, helm_solve_opts o, double scale, double* misfit,
+                            float* grad, int* iters, hipStream_t s, Owned& own) {
+    const long N = ops[0]->n();
+    const int nfs = nfreq * nper;
     c128* u = own.get<c128>((size_t)nfs * N);
     c128* lam = own.get<c128>((size_t)nfs * N);
     double* gacc = own.get<double>(N);
     double* part = own.get<double>(nfs);
-    int* src_d = own.get<int>(nsrc);
-    int* rec_d = own.get<int>(nrec);
-    if (!rhs || !u || !lam || !gacc || !part || !src_d || !rec_d)
-        return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
-    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
-    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
-
+    if (!u || !lam || !gacc || !part) return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
     std::vector<int> rhs_op(nfs);
-    for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nsrc;
+    for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nper;
     std::vector<int> st(nfs), it(nfs);
 
     // forward solves
-    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
-    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
-    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
-    HELM_CHECK_LAUNCH();
     int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, u, nfs, tol, &o, it.data(), nullptr, st.data(), s);
     if (rc < 0) return rc;
     int worst = rc;
@@ -150,7 +175,7 @@ extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_i
 
     // residuals, misfit, adjoint sources
     HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
-    hipLaunchKernelGGL(k_fwi_residual, dim3(nfs), dim3(256), 0, s, u, (const c64*)dobs, rec_d, nrec, N, rhs, part);
+    hipLaunchKernelGGL(k_fwi_residual, dim3(nfs), dim3(256), 0, s, u, dobs_d, rec_d, nrec, N, rhs, part);
     HELM_CHECK_LAUNCH();
     std::vector<double> ph(nfs);
     HELM_HIP(hipMemcpyAsync(ph.data(), part, sizeof(double) * nfs, hipMemcpyDeviceToHost, s));
@@ -165,9 +190,9 @@ extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_i
     // gradient, frequency by frequency in a fixed order
     const int nb = (int)((N + 255) / 256);
     for (int f = 0; f < nfreq; ++f) {
-        const double w2 = ops[f]->omega * ops[f]->omega;
-        hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
-                           lam + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g, w2, nsrc, N, f == 0 ? 1 : 0,
+        const double w2 = ops[f]->omega * ops[f]->omega * scale;
+        hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nper * N,
+                           lam + (size_t)f * nper * N, (const float*)ops[f]->lv[0].g, w2, nper, N, f == 0 ? 1 : 0,
                            gacc);
         HELM_CHECK_LAUNCH();
     }
@@ -176,6 +201,89 @@ extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_i
     HELM_HIP(hipStreamSynchronize(s));
     double phi = 0;
     for (int i = 0; i < nfs; ++i) phi += ph[i];
-    *misfit = phi;
+    *misfit = phi * scale;
     return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}
+
+static int solve_opts(const helm_solve_opts* opt, const char* name, helm_solve_opts* o) {
+    memset(o, 0, sizeof(*o));
+    if (opt) *o = *opt;
+    if (o->adjoint) return fail(HELM_EINVAL, "%s: opts.adjoint must be 0 (the call runs both solves)", name);
+    o->x0_given = 0;
+    return HELM_OK;
+}
+
+}  // namespace
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
+                               int nrec, const void* dobs, double tol, const helm_solve_opts* opt, double* misfit,
+                               float* grad, int* iters, void* stream) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit || !grad)
+        return fail(HELM_EINVAL, "fwi_misfit_grad: bad arguments");
+    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad: tol must be positive");
+    int rc = check_args("fwi_misfit_grad", ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    if (rc) return rc;
+    helm_solve_opts o;
+    if ((rc = solve_opts(opt, "fwi_misfit_grad", &o))) return rc;
+
+    hipStream_t s = (hipStream_t)stream;
+    const long N = ops[0]->n();
+    const int nfs = nfreq * nsrc;
+    Owned own;
+    c64* rhs = own.get<c64>((size_t)nfs * N);
+    int* src_d = own.get<int>(nsrc);
+    int* rec_d = own.get<int>(nrec);
+    if (!rhs || !src_d || !rec_d) return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
+    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
+    HELM_CHECK_LAUNCH();
+    return misfit_grad_core(ops, nfreq, nsrc, rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, iters, s,
+                            own);
+}
+
+extern "C" int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
+                                       const float* X, int p, const int* rec_idx, int nrec, const void* dobs,
+                                       double tol, const helm_solve_opts* opt, double* misfit, float* grad,
+                                       int* iters, void* stream) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !X || p <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit ||
+        !grad)
+        return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: bad arguments");
+    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: tol must be positive");
+    int rc = check_args("fwi_misfit_grad_encoded", ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    if (rc) return rc;
+    for (long q = 0; q < (long)nsrc * p; ++q)
+        if (!std::isfinite(X[q])) return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: X has a non-finite entry");
+    helm_solve_opts o;
+    if ((rc = solve_opts(opt, "fwi_misfit_grad_encoded", &o))) return rc;
+
+    hipStream_t s = (hipStream_t)stream;
+    const long N = ops[0]->n();
+    const int nfp = nfreq * p;
+    Owned own;
+    c64* rhs = own.get<c64>((size_t)nfp * N);
+    c64* dx = own.get<c64>((size_t)nfp * nrec);
+    float* X_d = own.get<float>((size_t)nsrc * p);
+    int* src_d = own.get<int>(nsrc);
+    int* rec_d = own.get<int>(nrec);
+    if (!rhs || !dx || !X_d || !src_d || !rec_d)
+        return fail(HELM_ENOMEM, "fwi_misfit_grad_encoded: workspace allocation failed");
+    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(X_d, X, sizeof(float) * (size_t)nsrc * p, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfp * N, s));
+    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+    hipLaunchKernelGGL(k_encoded_sources, dim3((nfp + 255) / 256), dim3(256), 0, s, src_d, X_d, nsrc, p, nfp, N, amp,
+                       rhs);
+    HELM_CHECK_LAUNCH();
+    const long total = (long)nfp * nrec;
+    hipLaunchKernelGGL(k_encode_data, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const c64*)dobs, X_d,
+                       nsrc, p, nrec, total, dx);
+    HELM_CHECK_LAUNCH();
+    return misfit_grad_core(ops, nfreq, p, rhs, dx, rec_d, nrec, tol, o, 1.0 / p, misfit, grad, iters, s, own);
 }

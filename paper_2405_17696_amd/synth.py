@@ -180,6 +180,12 @@ def surface_positions(nx: int, count: int, width: int = ABL_WIDTH) -> np.ndarray
     return np.array([width + int(round((s + 0.5) * span / count)) for s in range(count)], dtype=np.int64)
 
 
+def rademacher(nsrc: int, p: int, rng: np.random.Generator) -> np.ndarray:
+    """nsrc x p matrix of independent +-1 entries (the simultaneous-source
+    encoding draws), float32."""
+    return np.where(rng.random((nsrc, p)) < 0.5, -1.0, 1.0).astype(np.float32)
+
+
 def point_sources(nz: int, nx: int, cols: np.ndarray, row: int = 4, h: float = H_DEFAULT,
                   hz: float | None = None) -> np.ndarray:
     """Grid deltas e_s/(hx*hz) at (row, col) for each col; complex64 [ns][nz][nx]."""

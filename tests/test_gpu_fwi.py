@@ -1,6 +1,8 @@
 """FWI misfit and gradient through the library (eq. 3.5, 3.10, 4.8) against the
 oracle's SuperLU-based adjoint-state gradient, central differences of the
-library's own misfit, and the torch.autograd.Function wrapper."""
+library's own misfit, and the torch.autograd.Function wrapper; the
+simultaneous-source variant (eq. 3.6-3.8) against the oracle's encoded misfit
+and, for the identity encoding, against the unencoded call."""
 import numpy as np
 import pytest
 import torch
@@ -114,3 +116,53 @@ def test_bad_arguments(gpu):
         gpu_call(k2, gamma, omegas, h, src, np.array([rec[0], rec[0], *rec[2:]]), dobs)
     with pytest.raises(L.HelmError):        # index out of range
         gpu_call(k2, gamma, omegas, h, np.array([k2.size]), rec, dobs[:, :1])
+
+
+def gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, X, **kw):
+    kd = torch.tensor(k2, dtype=torch.float32, device="cuda")
+    gd = torch.tensor(gamma, dtype=torch.float32, device="cuda")
+    ops = [api.helm_setup(kd, gd, w, h) for w in omegas]
+    d = torch.tensor(dobs, dtype=torch.complex64, device="cuda")
+    phi, g, its, code = api.fwi_misfit_grad_encoded(ops, src, X, rec, d, **kw)
+    for o in ops:
+        o.close()
+    return phi, g.cpu().numpy().astype(np.float64), its, code
+
+
+@pytest.mark.parametrize("kw,tol_g", [
+    (dict(tol=1e-6), 1e-3),
+    (dict(tol=1e-10, krylov_dtype="c128"), 1e-6),
+])
+def test_encoded_gradient_matches_oracle(gpu, kw, tol_g):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nsrc=6, nrec=8)
+    X = synth.rademacher(len(src), 3, np.random.default_rng(21))
+    print("fwi encoded parity", kw, flush=True)
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    phi_o, g_o = fwi.misfit_and_grad_encoded(k2, gamma, omegas, h, src, rec, dobs, X.astype(np.float64))
+    phi, g, its, code = gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, X, **kw)
+    assert code == 0
+    assert its.shape == (2, len(omegas), 3) and (its > 0).all()
+    assert abs(phi - phi_o) <= 10 * tol_g * phi_o
+    assert relerr(g, g_o) <= tol_g
+
+
+def test_encoded_identity_is_unencoded_over_nsrc(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nsrc=4, nrec=6)
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    ns = len(src)
+    phi, g, its, code = gpu_call(k2, gamma, omegas, h, src, rec, dobs, tol=1e-6)
+    phx, gx, itx, codex = gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, np.eye(ns, dtype=np.float32),
+                                           tol=1e-6)
+    assert code == 0 and codex == 0 and np.array_equal(its, itx)
+    assert abs(phx * ns - phi) <= 1e-12 * phi
+    assert relerr(gx * ns, g) <= 1e-6
+
+
+def test_encoded_bad_arguments(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nsrc=2, nrec=3)
+    X = np.ones((2, 2), np.float32)
+    X[1, 1] = np.nan
+    with pytest.raises(L.HelmError, match="non-finite"):
+        gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, X)
+    with pytest.raises(ValueError):
+        gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, np.ones((3, 2), np.float32))
