@@ -17,7 +17,9 @@ oracle can compute one by one and on properties that hold at any size.
   generation for the same sample indices;
 * 512 x 512 FWI setting (four frequencies, 128 receivers on row 4): the misfit
   gradient against the oracle's adjoint-state gradient, with two of the 128
-  sources (the oracle factorises each frequency once).
+  sources (the oracle factorises each frequency once); and the
+  simultaneous-source gradient on the same grid with 8 of the sources encoded
+  into 4 (two of the frequencies).
 """
 import numpy as np
 import pytest
@@ -139,3 +141,25 @@ def test_retraining_pairs_full_size(gpu):
         R0, E0, ks = T.make_pairs(coef, med.h, med.h, V, (n, n), 1, seed=seed, first=i)
         print("pair", i, "k", ks, "e rel", relerr(es[t], E0[0]), flush=True)
         assert relerr(es[t], E0[0]) <= 2e-3 and relerr(rs[t], R0[0]) <= 2e-3
+
+
+def test_fwi_encoded_gradient_full_grid(gpu):
+    d = synth.config5_media(nsrc=128, nrec=128)
+    k2 = f32(d["kappa2_init"])
+    kt = f32(d["kappa2_true"])
+    gam = f32(d["gamma"])
+    src = np.asarray(d["src_idx"])[::16]
+    rec = np.asarray(d["rec_idx"])
+    h, omegas = d["h"], d["omegas"][:2]
+    X = synth.rademacher(len(src), 4, np.random.default_rng(55))
+    print("full-grid encoded fwi gradient", len(src), "sources into", X.shape[1], flush=True)
+    dobs = fwi.forward_data(kt, gam, omegas, h, src, rec).astype(np.complex64).astype(np.complex128)
+    phi_o, g_o = fwi.misfit_and_grad_encoded(k2, gam, omegas, h, src, rec, dobs, X.astype(np.float64))
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    ops = [api.helm_setup(t(k2), t(gam), w, h) for w in omegas]
+    phi, g, its, code = api.fwi_misfit_grad_encoded(ops, src, X, rec,
+                                                    torch.tensor(dobs, dtype=torch.complex64, device="cuda"),
+                                                    tol=1e-6, precond="mg", maxit=3000, restart=20)
+    assert code == 0 and its.shape == (2, 2, 4)
+    assert abs(phi - phi_o) <= 1e-2 * phi_o
+    assert relerr(g.cpu().numpy().astype(np.float64), g_o) <= 1e-3
