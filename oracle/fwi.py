@@ -29,6 +29,10 @@ The encoded misfit and its gradient are those above with the p encoded
 sources G x_i and encoded data D_f x_i in place of the ns point sources, and a
 factor 1/p.
 
+Gauss-Newton (eq. 3.9-3.11): the Hessian of the misfit without its
+second-order term, applied to a model perturbation, is Re(J^H J dm), with
+J dm from born and Re(J^H dd) from born_adjoint.
+
 All solves are SuperLU factorisations in complex128.
 """
 from __future__ import annotations
@@ -150,3 +154,10 @@ def misfit_and_grad_encoded(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, X
         lam = np.conj(S.solve(np.conj(src_adj)))
         grad += np.sum(np.real(np.conj(lam) * (w ** 2) * (1.0 - 1j * gam) * u), axis=0) / p
     return phi, grad.reshape(nz, nx)
+
+
+def gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz=None):
+    """Gauss-Newton Hessian times a model perturbation, Re(J^H J dm) (the
+    misfit's Hessian without its second-order term, eq. 3.9-3.11), float64 [nz][nx]."""
+    jdm = born(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz)
+    return born_adjoint(kappa2, gamma, omegas, hx, src_idx, rec_idx, jdm, hz)

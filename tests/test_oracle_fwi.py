@@ -134,3 +134,25 @@ def test_encoded_gradient_central_differences():
         fm = fwi.misfit_and_grad_encoded(k2 - eps * d, gamma, omegas, h, src, rec, dobs, X)[0]
         fd = (fp - fm) / (2 * eps)
         assert abs(np.sum(g * d) - fd) <= 1e-5 * abs(fd), (t, np.sum(g * d), fd)
+
+
+def test_born_is_the_derivative_of_the_data():
+    # J dm against central differences of the forward data (the sign of eq. 3.10 decided here too)
+    k2, gamma, omegas, h, src, rec, _ = small_problem()
+    dm = np.random.default_rng(31).standard_normal(k2.shape)
+    jdm = fwi.born(k2, gamma, omegas, h, src, rec, dm)
+    eps = 1e-4 * np.abs(k2).max() / np.abs(dm).max()
+    fd = (fwi.forward_data(k2 + eps * dm, gamma, omegas, h, src, rec)
+          - fwi.forward_data(k2 - eps * dm, gamma, omegas, h, src, rec)) / (2 * eps)
+    assert np.linalg.norm(jdm - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_gn_hessvec_symmetric_positive_and_norm_of_jv():
+    k2, gamma, omegas, h, src, rec, _ = small_problem()
+    rng = np.random.default_rng(32)
+    v, w = rng.standard_normal(k2.shape), rng.standard_normal(k2.shape)
+    hv = fwi.gn_hessvec(k2, gamma, omegas, h, src, rec, v)
+    hw = fwi.gn_hessvec(k2, gamma, omegas, h, src, rec, w)
+    assert abs(np.sum(w * hv) - np.sum(v * hw)) <= 1e-10 * abs(np.sum(v * hw))
+    jv = fwi.born(k2, gamma, omegas, h, src, rec, v)
+    assert abs(np.sum(v * hv) - np.linalg.norm(jv) ** 2) <= 1e-10 * np.linalg.norm(jv) ** 2
