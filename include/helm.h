@@ -263,6 +263,32 @@ int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const int* src_idx,
                             double* misfit, float* grad, int* iters, void* stream);
 
 /*
+ * Linearised data (Gauss-Newton, eq. (3.9)-(3.11); the Jacobian's sign derived
+ * from eq. (3.1)): with the point-source fields u_fs = H_f^{-1} g_s of the
+ * operators' model m,
+ *   fwi_born:          jdm = J dm,  J dm_fs = R H_f^{-1} (w_f^2 (1 - i gamma) u_fs dm),
+ *                      dm float [nz][nx] (device) -> jdm c64 [nfreq][nsrc][nrec] (device);
+ *   fwi_born_adjoint:  out = Re(J^H dd) = sum_fs w_f^2 Re(conj(lambda_fs) (1 - i gamma) u_fs),
+ *                      lambda_fs = H_f^{-*} R^T dd_fs by conjugation (eq. (4.8)),
+ *                      dd c64 [nfreq][nsrc][nrec] (device) -> out float [nz][nx] (device);
+ *   fwi_gn_hessvec:    out = Re(J^H J dm), the Gauss-Newton Hessian of the misfit
+ *                      applied to dm (what CG on the Gauss-Newton system needs).
+ * Sources, receivers, tol and opt as for fwi_misfit_grad.  iters (host, may be
+ * NULL) receives [nfreq][nsrc] per solve batch: forward then Born (fwi_born),
+ * forward then adjoint (fwi_born_adjoint), forward, Born, adjoint
+ * (fwi_gn_hessvec).  Each batch is one helm_solve call over all (f, s).
+ * Workspace is allocated and freed inside the call.  Returns HELM_OK,
+ * HELM_NOT_CONVERGED if any solve missed tol (outputs still written), or a hard
+ * error.
+ */
+int fwi_born(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+             const float* dm, double tol, const helm_solve_opts* opt, void* jdm, int* iters, void* stream);
+int fwi_born_adjoint(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                     const void* dd, double tol, const helm_solve_opts* opt, float* out, int* iters, void* stream);
+int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                   const float* dm, double tol, const helm_solve_opts* opt, float* out, int* iters, void* stream);
+
+/*
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
  * times every applicable kernel (halo-tiled persistent with 16 or 32 output

@@ -404,6 +404,62 @@ def fwi_misfit_grad_encoded(ops, src_idx, X, rec_idx, dobs: torch.Tensor, tol: f
     return phi.value, grad, np.array(its[:], dtype=np.int64).reshape(2, nf, p), code
 
 
+def _fwi_lin(name, ops, src_idx, rec_idx, x: torch.Tensor, tol, precond, restart, maxit, krylov_dtype, use_graph,
+             reorth, net):
+    """Shared marshalling of fwi_born / fwi_born_adjoint / fwi_gn_hessvec."""
+    import numpy as np
+    lib = L.load()
+    if isinstance(ops, HelmOp):
+        ops = [ops]
+    src = [int(v) for v in np.asarray(src_idx).ravel()]
+    rec = [int(v) for v in np.asarray(rec_idx).ravel()]
+    nf, ns, nr = len(ops), len(src), len(rec)
+    if name == "fwi_born_adjoint":
+        if x.dtype != torch.complex64 or tuple(x.shape) != (nf, ns, nr):
+            raise ValueError(f"dd must be complex64 of shape {(nf, ns, nr)}")
+        out = torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=x.device)
+    else:
+        if x.dtype != torch.float32 or x.numel() != ops[0].n:
+            raise ValueError("dm must be float32 [nz][nx]")
+        out = (torch.empty((nf, ns, nr), dtype=torch.complex64, device=x.device) if name == "fwi_born" else
+               torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=x.device))
+    x = x.contiguous()
+    handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
+                    L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+    nb = 3 if name == "fwi_gn_hessvec" else 2
+    its = (C.c_int * (nb * nf * ns))()
+    code = getattr(lib, name)(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(x), float(tol),
+                              C.byref(o), _ptr(out), its, _stream())
+    L.check(code, soft_ok=True)
+    return out, np.array(its[:], dtype=np.int64).reshape(nb, nf, ns), code
+
+
+def fwi_born(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, precond: str = "mg", restart: int = 0,
+             maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None):
+    """J dm: linearised data, complex64 [nfreq][nsrc][nrec].  Returns (jdm, iters [2][nfreq][nsrc], code)."""
+    return _fwi_lin("fwi_born", ops, src_idx, rec_idx, dm, tol, precond, restart, maxit, krylov_dtype, use_graph,
+                    reorth, net)
+
+
+def fwi_born_adjoint(ops, src_idx, rec_idx, dd: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
+                     restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
+                     reorth: bool = False, net=None):
+    """Re(J^H dd), float32 [nz][nx].  Returns (out, iters [2][nfreq][nsrc], code)."""
+    return _fwi_lin("fwi_born_adjoint", ops, src_idx, rec_idx, dd, tol, precond, restart, maxit, krylov_dtype,
+                    use_graph, reorth, net)
+
+
+def fwi_gn_hessvec(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
+                   restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
+                   reorth: bool = False, net=None):
+    """Re(J^H J dm), the Gauss-Newton Hessian applied to dm, float32 [nz][nx].
+    Returns (out, iters [3][nfreq][nsrc], code)."""
+    return _fwi_lin("fwi_gn_hessvec", ops, src_idx, rec_idx, dm, tol, precond, restart, maxit, krylov_dtype,
+                    use_graph, reorth, net)
+
+
 class FwiMisfit(torch.autograd.Function):
     """Phi(m) = 1/2 sum_{f,s} |R H_f(m)^{-1} g_s - d_fs|^2 as a differentiable function
     of the squared slowness m (float32 [nz][nx] on the GPU).  The forward pass runs

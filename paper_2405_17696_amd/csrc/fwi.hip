@@ -109,6 +109,36 @@ __global__ void k_fwi_grad_freq(const c128* __restrict__ u, const c128* __restri
     gacc[k] = first ? w2 * acc : gacc[k] + w2 * acc;
 }
 
+// Born sources of one frequency: rhs_s = w^2 (1 - i gamma) u_s dm (c64), nper fields.
+__global__ void k_born_source(const c128* __restrict__ u, const float* __restrict__ gam, const float* __restrict__ dm,
+                              double w2, int nper, long N, c64* __restrict__ rhs) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double g = gam[k], d = w2 * (double)dm[k];
+    for (int s = 0; s < nper; ++s) {
+        const c128 a = u[(long)s * N + k];
+        // (1 - i g) u = (u.re + g u.im) + i (u.im - g u.re)
+        rhs[(long)s * N + k] = c64{(float)(d * (a.re + g * a.im)), (float)(d * (a.im - g * a.re))};
+    }
+}
+
+// out[fs][r] = field fs at receiver r (c64).
+__global__ void k_sample_rec(const c128* __restrict__ u, const int* __restrict__ rec, int nrec, long N, long total,
+                             c64* __restrict__ out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const c128 v = u[(t / nrec) * N + rec[t % nrec]];
+    out[t] = c64{(float)v.re, (float)v.im};
+}
+
+// R^T dd into the zeroed rhs: rhs[fs][rec[r]] = dd[fs][r].
+__global__ void k_scatter_rec(const c64* __restrict__ dd, const int* __restrict__ rec, int nrec, long N, long total,
+                              c64* __restrict__ rhs) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    rhs[(t / nrec) * N + rec[t % nrec]] = dd[t];
+}
+
 __global__ void k_to_float(const double* __restrict__ a, long n, float* __restrict__ b) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) b[t] = (float)a[t];
@@ -205,6 +235,83 @@ static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs,
     return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
 }
 
+// Linearised data and its adjoint (eq. 3.10, with the sign derived from
+// eq. 3.1): from the point-source fields u_fs,
+//   J dm      = R H_f^{-1} (w_f^2 (1 - i gamma) u_fs dm)          (when dm != NULL)
+//   Re(J^H d) = sum_fs w_f^2 Re(conj(H_f^{-*} R^T d_fs) (1 - i gamma) u_fs)
+// with d = dd, or d = J dm when dd is NULL (the Gauss-Newton product).  jdm
+// (device c64 [nfreq][nsrc][nrec], may be NULL) receives J dm, out (device
+// float [nz][nx], may be NULL) Re(J^H d); iters receives one [nfreq][nsrc]
+// block per solve batch in the order forward, Born, adjoint.
+static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d, int nrec,
+                     const float* dm, const c64* dd, c64* jdm, float* out, double tol, helm_solve_opts o, int* iters,
+                     hipStream_t s, Owned& own) {
+    const long N = ops[0]->n();
+    const int nfs = nfreq * nsrc;
+    const long nd = (long)nfs * nrec;
+    c64* rhs = own.get<c64>((size_t)nfs * N);
+    c128* u = own.get<c128>((size_t)nfs * N);
+    c128* w = own.get<c128>((size_t)nfs * N);
+    c64* jd = jdm ? jdm : own.get<c64>((size_t)nd);
+    double* gacc = own.get<double>(N);
+    if (!rhs || !u || !w || !jd || !gacc) return fail(HELM_ENOMEM, "fwi born: workspace allocation failed");
+    std::vector<int> rhs_op(nfs);
+    for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nsrc;
+    std::vector<int> st(nfs), it(nfs);
+    int worst = HELM_OK, stage = 0;
+    auto solve = [&](c128* x, int adjoint) {
+        o.adjoint = adjoint;
+        const int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, x, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+        if (rc >= 0) {
+            worst = std::max(worst, rc);
+            if (iters) std::copy(it.begin(), it.end(), iters + (size_t)stage * nfs);
+            ++stage;
+        }
+        return rc;
+    };
+    const unsigned gd = (unsigned)((nd + 255) / 256);
+    const int nb = (int)((N + 255) / 256);
+    int rc;
+
+    // point-source fields
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
+    HELM_CHECK_LAUNCH();
+    if ((rc = solve(u, 0)) < 0) return rc;
+
+    // J dm
+    if (dm) {
+        for (int f = 0; f < nfreq; ++f) {
+            hipLaunchKernelGGL(k_born_source, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
+                               (const float*)ops[f]->lv[0].g, dm, ops[f]->omega * ops[f]->omega, nsrc, N,
+                               rhs + (size_t)f * nsrc * N);
+            HELM_CHECK_LAUNCH();
+        }
+        if ((rc = solve(w, 0)) < 0) return rc;
+        hipLaunchKernelGGL(k_sample_rec, dim3(gd), dim3(256), 0, s, w, rec_d, nrec, N, nd, jd);
+        HELM_CHECK_LAUNCH();
+    }
+
+    // Re(J^H d)
+    if (out) {
+        HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+        hipLaunchKernelGGL(k_scatter_rec, dim3(gd), dim3(256), 0, s, dd ? dd : jd, rec_d, nrec, N, nd, rhs);
+        HELM_CHECK_LAUNCH();
+        if ((rc = solve(w, 1)) < 0) return rc;
+        for (int f = 0; f < nfreq; ++f) {
+            hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
+                               w + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g, ops[f]->omega * ops[f]->omega,
+                               nsrc, N, f == 0 ? 1 : 0, gacc);
+            HELM_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, gacc, N, out);
+        HELM_CHECK_LAUNCH();
+    }
+    HELM_HIP(hipStreamSynchronize(s));
+    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}
+
 static int solve_opts(const helm_solve_opts* opt, const char* name, helm_solve_opts* o) {
     memset(o, 0, sizeof(*o));
     if (opt) *o = *opt;
@@ -286,4 +393,49 @@ extern "C" int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const in
                        nsrc, p, nrec, total, dx);
     HELM_CHECK_LAUNCH();
     return misfit_grad_core(ops, nfreq, p, rhs, dx, rec_d, nrec, tol, o, 1.0 / p, misfit, grad, iters, s, own);
+}
+
+// Shared set-up of the three linearised entry points.
+static int born_entry(const char* name, const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
+                      const int* rec_idx, int nrec, const float* dm, const void* dd, void* jdm, float* out, double tol,
+                      const helm_solve_opts* opt, int* iters, void* stream) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0)
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    if (rc) return rc;
+    helm_solve_opts o;
+    if ((rc = solve_opts(opt, name, &o))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    int* src_d = own.get<int>(nsrc);
+    int* rec_d = own.get<int>(nrec);
+    if (!src_d || !rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+    return born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, dm, (const c64*)dd, (c64*)jdm, out, tol, o, iters, s, own);
+}
+
+extern "C" int fwi_born(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                        const float* dm, double tol, const helm_solve_opts* opt, void* jdm, int* iters,
+                        void* stream) {
+    if (!dm || !jdm) return fail(HELM_EINVAL, "fwi_born: bad arguments");
+    return born_entry("fwi_born", ops, nfreq, src_idx, nsrc, rec_idx, nrec, dm, nullptr, jdm, nullptr, tol, opt, iters,
+                      stream);
+}
+
+extern "C" int fwi_born_adjoint(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
+                                int nrec, const void* dd, double tol, const helm_solve_opts* opt, float* out,
+                                int* iters, void* stream) {
+    if (!dd || !out) return fail(HELM_EINVAL, "fwi_born_adjoint: bad arguments");
+    return born_entry("fwi_born_adjoint", ops, nfreq, src_idx, nsrc, rec_idx, nrec, nullptr, dd, nullptr, out, tol,
+                      opt, iters, stream);
+}
+
+extern "C" int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
+                              int nrec, const float* dm, double tol, const helm_solve_opts* opt, float* out,
+                              int* iters, void* stream) {
+    if (!dm || !out) return fail(HELM_EINVAL, "fwi_gn_hessvec: bad arguments");
+    return born_entry("fwi_gn_hessvec", ops, nfreq, src_idx, nsrc, rec_idx, nrec, dm, nullptr, nullptr, out, tol, opt,
+                      iters, stream);
 }

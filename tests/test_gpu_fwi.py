@@ -166,3 +166,55 @@ def test_encoded_bad_arguments(gpu):
         gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, X)
     with pytest.raises(ValueError):
         gpu_call_encoded(k2, gamma, omegas, h, src, rec, dobs, np.ones((3, 2), np.float32))
+
+
+def lin_ops(k2, gamma, omegas, h):
+    kd = torch.tensor(k2, dtype=torch.float32, device="cuda")
+    gd = torch.tensor(gamma, dtype=torch.float32, device="cuda")
+    return [api.helm_setup(kd, gd, w, h) for w in omegas]
+
+
+@pytest.mark.parametrize("kw,tol", [(dict(tol=1e-6), 1e-3), (dict(tol=1e-10, krylov_dtype="c128"), 1e-6)])
+def test_born_adjoint_born_and_gn_hessvec_match_oracle(gpu, kw, tol):
+    k2, gamma, omegas, h, src, rec, dobs = problem()
+    rng = np.random.default_rng(41)
+    dm = rng.standard_normal(k2.shape).astype(np.float32)
+    dd = (rng.standard_normal(dobs.shape) + 1j * rng.standard_normal(dobs.shape)).astype(np.complex64)
+    ops = lin_ops(k2, gamma, omegas, h)
+    print("born / adjoint / gn", kw, flush=True)
+    jdm, its, code = api.fwi_born(ops, src, rec, torch.tensor(dm, device="cuda"), **kw)
+    assert code == 0 and its.shape == (2, len(omegas), len(src)) and (its > 0).all()
+    jdm_o = fwi.born(k2, gamma, omegas, h, src, rec, dm.astype(np.float64))
+    assert relerr(jdm.cpu().numpy().astype(np.complex128), jdm_o) <= tol
+    ja, its, code = api.fwi_born_adjoint(ops, src, rec, torch.tensor(dd, device="cuda"), **kw)
+    assert code == 0
+    ja_o = fwi.born_adjoint(k2, gamma, omegas, h, src, rec, dd.astype(np.complex128))
+    assert relerr(ja.cpu().numpy().astype(np.float64), ja_o) <= tol
+    hv, its, code = api.fwi_gn_hessvec(ops, src, rec, torch.tensor(dm, device="cuda"), **kw)
+    assert code == 0 and its.shape == (3, len(omegas), len(src))
+    hv_o = fwi.gn_hessvec(k2, gamma, omegas, h, src, rec, dm.astype(np.float64))
+    assert relerr(hv.cpu().numpy().astype(np.float64), hv_o) <= tol
+    for o in ops:
+        o.close()
+
+
+def test_born_pair_dot_product_and_gn_quadratic_form(gpu):
+    # all on the library: <dd, J dm> = <J^H dd, dm>, and dm . (J^H J dm) = ||J dm||^2
+    k2, gamma, omegas, h, src, rec, dobs = problem(nsrc=2, nrec=5)
+    rng = np.random.default_rng(42)
+    dm = torch.tensor(rng.standard_normal(k2.shape).astype(np.float32), device="cuda")
+    dd = torch.tensor((rng.standard_normal(dobs.shape) + 1j * rng.standard_normal(dobs.shape)).astype(np.complex64),
+                      device="cuda")
+    ops = lin_ops(k2, gamma, omegas, h)
+    kw = dict(tol=1e-10, krylov_dtype="c128")
+    jdm, _, _ = api.fwi_born(ops, src, rec, dm, **kw)
+    ja, _, _ = api.fwi_born_adjoint(ops, src, rec, dd, **kw)
+    hv, _, _ = api.fwi_gn_hessvec(ops, src, rec, dm, **kw)
+    lhs = float(torch.real(torch.vdot(dd.reshape(-1).to(torch.complex128), jdm.reshape(-1).to(torch.complex128))))
+    rhs = float((ja.double() * dm.double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    quad = float((hv.double() * dm.double()).sum())
+    nrm2 = float((jdm.to(torch.complex128).abs() ** 2).sum())
+    assert abs(quad - nrm2) <= 1e-5 * nrm2
+    for o in ops:
+        o.close()
