@@ -19,7 +19,8 @@ oracle can compute one by one and on properties that hold at any size.
   gradient against the oracle's adjoint-state gradient, with two of the 128
   sources (the oracle factorises each frequency once); and the
   simultaneous-source gradient on the same grid with 8 of the sources encoded
-  into 4 (two of the frequencies).
+  into 4 (two of the frequencies), and the Gauss-Newton Hessian-vector
+  product there with two sources and two frequencies.
 """
 import numpy as np
 import pytest
@@ -163,3 +164,20 @@ def test_fwi_encoded_gradient_full_grid(gpu):
     assert code == 0 and its.shape == (2, 2, 4)
     assert abs(phi - phi_o) <= 1e-2 * phi_o
     assert relerr(g.cpu().numpy().astype(np.float64), g_o) <= 1e-3
+
+
+def test_gn_hessvec_full_grid(gpu):
+    d = synth.config5_media(nsrc=128, nrec=128)
+    k2 = f32(d["kappa2_init"])
+    gam = f32(d["gamma"])
+    src = np.asarray(d["src_idx"])[[30, 100]]
+    rec = np.asarray(d["rec_idx"])
+    h, omegas = d["h"], d["omegas"][1:3]
+    dm = (f32(d["kappa2_true"]) - k2).astype(np.float32)
+    print("full-grid Gauss-Newton product", flush=True)
+    hv_o = fwi.gn_hessvec(k2, gam, omegas, h, src, rec, dm.astype(np.float64))
+    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    ops = [api.helm_setup(t(k2), t(gam), w, h) for w in omegas]
+    hv, its, code = api.fwi_gn_hessvec(ops, src, rec, t(dm), tol=1e-6, precond="mg", maxit=3000, restart=20)
+    assert code == 0 and its.shape == (3, 2, 2)
+    assert relerr(hv.cpu().numpy().astype(np.float64), hv_o) <= 1e-3
