@@ -31,7 +31,8 @@ factor 1/p.
 
 Gauss-Newton (eq. 3.9-3.11): the Hessian of the misfit without its
 second-order term, applied to a model perturbation, is Re(J^H J dm), with
-J dm from born and Re(J^H dd) from born_adjoint.
+J dm from born and Re(J^H dd) from born_adjoint.  gn_cg is textbook conjugate
+gradients on the damped system (Re(J^H J) + damping I) x = b built on it.
 
 All solves are SuperLU factorisations in complex128.
 """
@@ -161,3 +162,26 @@ def gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz=None):
     misfit's Hessian without its second-order term, eq. 3.9-3.11), float64 [nz][nx]."""
     jdm = born(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz)
     return born_adjoint(kappa2, gamma, omegas, hx, src_idx, rec_idx, jdm, hz)
+
+
+def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=None):
+    """Conjugate gradients on the damped Gauss-Newton system (Re(J^H J) + damping I) x = b
+    from x = 0 (the inner solve of a Gauss-Newton step, Sec. 3.3), `iters` steps.
+    Returns x (float64 [nz][nx]) and the residual norms ||b - A x_k||, k = 0..iters."""
+    A = lambda v: gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, v, hz) + damping * v
+    b = np.asarray(b, np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    norms = [np.sqrt(rr)]
+    for _ in range(iters):
+        ap = A(p)
+        alpha = rr / float(np.sum(p * ap))
+        x = x + alpha * p
+        r = r - alpha * ap
+        rr_new = float(np.sum(r * r))
+        norms.append(np.sqrt(rr_new))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x, np.array(norms)

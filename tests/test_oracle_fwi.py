@@ -156,3 +156,26 @@ def test_gn_hessvec_symmetric_positive_and_norm_of_jv():
     assert abs(np.sum(w * hv) - np.sum(v * hw)) <= 1e-10 * abs(np.sum(v * hw))
     jv = fwi.born(k2, gamma, omegas, h, src, rec, v)
     assert abs(np.sum(v * hv) - np.linalg.norm(jv) ** 2) <= 1e-10 * np.linalg.norm(jv) ** 2
+
+
+def test_gn_cg_reaches_the_dense_solution():
+    # tiny grid: the damped Gauss-Newton matrix assembled column by column from
+    # gn_hessvec and solved densely; CG with as many steps as unknowns reaches it
+    k2, gamma, omegas, h, src, rec, _ = small_problem(nz=8, nx=8, nsrc=2, nrec=3)
+    n = k2.size
+    damping = 1e-3
+    cols = []
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        cols.append(fwi.gn_hessvec(k2, gamma, omegas, h, src, rec, e.reshape(k2.shape)).ravel())
+    A = np.array(cols).T + damping * np.eye(n)
+    assert np.abs(A - A.T).max() <= 1e-10 * np.abs(A).max()
+    b = np.random.default_rng(33).standard_normal(k2.shape)
+    x_dense = np.linalg.solve(A, b.ravel())
+    x, norms = fwi.gn_cg(k2, gamma, omegas, h, src, rec, b, damping, 3 * n)
+    assert np.linalg.norm(x.ravel() - x_dense) <= 1e-6 * np.linalg.norm(x_dense)
+    assert abs(norms[0] - np.linalg.norm(b)) <= 1e-12 * norms[0]
+    # after k steps the reported residual is b - A x_k
+    x3, n3 = fwi.gn_cg(k2, gamma, omegas, h, src, rec, b, damping, 3)
+    assert abs(n3[-1] - np.linalg.norm(b.ravel() - A @ x3.ravel())) <= 1e-8 * n3[0]
