@@ -289,6 +289,24 @@ int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc
                    const float* dm, double tol, const helm_solve_opts* opt, float* out, int* iters, void* stream);
 
 /*
+ * fwi_gn_cg -- cg_iters conjugate-gradient steps from x = 0 on the damped
+ * Gauss-Newton system (Re(J^H J) + damping I) x = b, the inner solve of a
+ * Gauss-Newton step (Sec. 3.3, eq. (3.9)-(3.11)), with the products of
+ * fwi_gn_hessvec: the point-source fields are computed once and reused, and
+ * each step costs one Born and one adjoint solve batch.
+ *   b, x: float [nz][nx] (device); the vector work is FP64 and dot products
+ *     are folded in a fixed order (same bits on every run);
+ *   resnorms (host, may be NULL): [cg_iters + 1] norms ||b - A x_k||;
+ *   damping >= 0; sources, receivers, tol and opt as for fwi_born.
+ * Stops early, with the remaining norms 0, when the residual is exactly 0.
+ * Returns as fwi_born, or HELM_ENAN if p.Ap <= 0 (a direction without
+ * curvature, possible only with damping 0).
+ */
+int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+              const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt, float* x,
+              double* resnorms, void* stream);
+
+/*
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
  * times every applicable kernel (halo-tiled persistent with 16 or 32 output

@@ -460,6 +460,34 @@ def fwi_gn_hessvec(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, p
                     use_graph, reorth, net)
 
 
+def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_iters: int = 10, tol: float = 1e-6,
+              precond: str = "mg", restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64",
+              use_graph: bool = False, reorth: bool = False, net=None):
+    """cg_iters CG steps on (Re(J^H J) + damping I) x = b from x = 0; b float32
+    [nz][nx] on the GPU.  Returns (x float32 [nz][nx], residual norms
+    [cg_iters + 1], code)."""
+    import numpy as np
+    lib = L.load()
+    if isinstance(ops, HelmOp):
+        ops = [ops]
+    src = [int(v) for v in np.asarray(src_idx).ravel()]
+    rec = [int(v) for v in np.asarray(rec_idx).ravel()]
+    nf, ns, nr = len(ops), len(src), len(rec)
+    if b.dtype != torch.float32 or b.numel() != ops[0].n:
+        raise ValueError("b must be float32 [nz][nx]")
+    b = b.contiguous()
+    x = torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=b.device)
+    handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
+                    L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+    norms = (C.c_double * (cg_iters + 1))()
+    code = lib.fwi_gn_cg(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(b), float(damping),
+                         int(cg_iters), float(tol), C.byref(o), _ptr(x), norms, _stream())
+    L.check(code, soft_ok=True)
+    return x, np.array(norms[:], dtype=np.float64), code
+
+
 class FwiMisfit(torch.autograd.Function):
     """Phi(m) = 1/2 sum_{f,s} |R H_f(m)^{-1} g_s - d_fs|^2 as a differentiable function
     of the squared slowness m (float32 [nz][nx] on the GPU).  The forward pass runs

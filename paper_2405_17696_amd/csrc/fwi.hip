@@ -139,6 +139,53 @@ __global__ void k_scatter_rec(const c64* __restrict__ dd, const int* __restrict_
     rhs[(t / nrec) * N + rec[t % nrec]] = dd[t];
 }
 
+// Conjugate-gradient vector work in FP64.  Dot products: CG_BLOCKS fixed blocks
+// sum fixed strided ranges in order and fold in a tree; the host adds the block
+// partials in order, so every run gives the same bits.
+constexpr int CG_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_cg_dot(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                                double* __restrict__ part) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double acc = 0;
+    for (long k = (long)blockIdx.x * 256 + tid; k < n; k += (long)CG_BLOCKS * 256) acc += a[k] * b[k];
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_f2d(const float* __restrict__ a, long n, double* __restrict__ b) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = (double)a[t];
+}
+
+// ap = hp + damping p
+__global__ void k_cg_ap(const float* __restrict__ hp, const double* __restrict__ p, double damping, long n,
+                        double* __restrict__ ap) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) ap[t] = (double)hp[t] + damping * p[t];
+}
+
+// x += alpha p, r -= alpha ap
+__global__ void k_cg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                        const double* __restrict__ ap, double alpha, long n) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    x[t] += alpha * p[t];
+    r[t] -= alpha * ap[t];
+}
+
+// p = r + beta p
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ r, double beta, long n) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = r[t] + beta * p[t];
+}
+
 __global__ void k_to_float(const double* __restrict__ a, long n, float* __restrict__ b) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) b[t] = (float)a[t];
@@ -235,8 +282,29 @@ static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs,
     return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
 }
 
+// Workspace of the linearised products: rhs (c64) and u, w (c128) per (f, s),
+// receiver data (c64) and the FP64 gradient accumulator.
+struct BornWork {
+    c64* rhs = nullptr;
+    c128* u = nullptr;
+    c128* w = nullptr;
+    c64* jd = nullptr;
+    double* gacc = nullptr;
+};
+
+static int born_alloc(Owned& own, long N, int nfs, long nd, BornWork& W) {
+    W.rhs = own.get<c64>((size_t)nfs * N);
+    W.u = own.get<c128>((size_t)nfs * N);
+    W.w = own.get<c128>((size_t)nfs * N);
+    W.jd = own.get<c64>((size_t)nd);
+    W.gacc = own.get<double>(N);
+    if (!W.rhs || !W.u || !W.w || !W.jd || !W.gacc) return fail(HELM_ENOMEM, "fwi born: workspace allocation failed");
+    return HELM_OK;
+}
+
 // Linearised data and its adjoint (eq. 3.10, with the sign derived from
-// eq. 3.1): from the point-source fields u_fs,
+// eq. 3.1): from the point-source fields u_fs (computed into W.u unless
+// have_u),
 //   J dm      = R H_f^{-1} (w_f^2 (1 - i gamma) u_fs dm)          (when dm != NULL)
 //   Re(J^H d) = sum_fs w_f^2 Re(conj(H_f^{-*} R^T d_fs) (1 - i gamma) u_fs)
 // with d = dd, or d = J dm when dd is NULL (the Gauss-Newton product).  jdm
@@ -245,23 +313,19 @@ static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs,
 // block per solve batch in the order forward, Born, adjoint.
 static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d, int nrec,
                      const float* dm, const c64* dd, c64* jdm, float* out, double tol, helm_solve_opts o, int* iters,
-                     hipStream_t s, Owned& own) {
+                     hipStream_t s, const BornWork& W, bool have_u) {
     const long N = ops[0]->n();
     const int nfs = nfreq * nsrc;
     const long nd = (long)nfs * nrec;
-    c64* rhs = own.get<c64>((size_t)nfs * N);
-    c128* u = own.get<c128>((size_t)nfs * N);
-    c128* w = own.get<c128>((size_t)nfs * N);
-    c64* jd = jdm ? jdm : own.get<c64>((size_t)nd);
-    double* gacc = own.get<double>(N);
-    if (!rhs || !u || !w || !jd || !gacc) return fail(HELM_ENOMEM, "fwi born: workspace allocation failed");
+    c64* jd = jdm ? jdm : W.jd;
     std::vector<int> rhs_op(nfs);
     for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nsrc;
     std::vector<int> st(nfs), it(nfs);
     int worst = HELM_OK, stage = 0;
     auto solve = [&](c128* x, int adjoint) {
         o.adjoint = adjoint;
-        const int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, x, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+        const int rc =
+            helm_solve(ops, nfreq, rhs_op.data(), W.rhs, x, nfs, tol, &o, it.data(), nullptr, st.data(), s);
         if (rc >= 0) {
             worst = std::max(worst, rc);
             if (iters) std::copy(it.begin(), it.end(), iters + (size_t)stage * nfs);
@@ -274,38 +338,41 @@ static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d
     int rc;
 
     // point-source fields
-    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
-    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
-    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
-    HELM_CHECK_LAUNCH();
-    if ((rc = solve(u, 0)) < 0) return rc;
+    if (!have_u) {
+        HELM_HIP(hipMemsetAsync(W.rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+        const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+        hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp,
+                           W.rhs);
+        HELM_CHECK_LAUNCH();
+        if ((rc = solve(W.u, 0)) < 0) return rc;
+    }
 
     // J dm
     if (dm) {
         for (int f = 0; f < nfreq; ++f) {
-            hipLaunchKernelGGL(k_born_source, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
+            hipLaunchKernelGGL(k_born_source, dim3(nb), dim3(256), 0, s, W.u + (size_t)f * nsrc * N,
                                (const float*)ops[f]->lv[0].g, dm, ops[f]->omega * ops[f]->omega, nsrc, N,
-                               rhs + (size_t)f * nsrc * N);
+                               W.rhs + (size_t)f * nsrc * N);
             HELM_CHECK_LAUNCH();
         }
-        if ((rc = solve(w, 0)) < 0) return rc;
-        hipLaunchKernelGGL(k_sample_rec, dim3(gd), dim3(256), 0, s, w, rec_d, nrec, N, nd, jd);
+        if ((rc = solve(W.w, 0)) < 0) return rc;
+        hipLaunchKernelGGL(k_sample_rec, dim3(gd), dim3(256), 0, s, W.w, rec_d, nrec, N, nd, jd);
         HELM_CHECK_LAUNCH();
     }
 
     // Re(J^H d)
     if (out) {
-        HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
-        hipLaunchKernelGGL(k_scatter_rec, dim3(gd), dim3(256), 0, s, dd ? dd : jd, rec_d, nrec, N, nd, rhs);
+        HELM_HIP(hipMemsetAsync(W.rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+        hipLaunchKernelGGL(k_scatter_rec, dim3(gd), dim3(256), 0, s, dd ? dd : jd, rec_d, nrec, N, nd, W.rhs);
         HELM_CHECK_LAUNCH();
-        if ((rc = solve(w, 1)) < 0) return rc;
+        if ((rc = solve(W.w, 1)) < 0) return rc;
         for (int f = 0; f < nfreq; ++f) {
-            hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nsrc * N,
-                               w + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g, ops[f]->omega * ops[f]->omega,
-                               nsrc, N, f == 0 ? 1 : 0, gacc);
+            hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, W.u + (size_t)f * nsrc * N,
+                               W.w + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g,
+                               ops[f]->omega * ops[f]->omega, nsrc, N, f == 0 ? 1 : 0, W.gacc);
             HELM_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, gacc, N, out);
+        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, W.gacc, N, out);
         HELM_CHECK_LAUNCH();
     }
     HELM_HIP(hipStreamSynchronize(s));
@@ -413,7 +480,10 @@ static int born_entry(const char* name, const helm_op_t* ops, int nfreq, const i
     if (!src_d || !rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
-    return born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, dm, (const c64*)dd, (c64*)jdm, out, tol, o, iters, s, own);
+    BornWork W;
+    if ((rc = born_alloc(own, ops[0]->n(), nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
+    return born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, dm, (const c64*)dd, (c64*)jdm, out, tol, o, iters, s, W,
+                     false);
 }
 
 extern "C" int fwi_born(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
@@ -438,4 +508,88 @@ extern "C" int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_id
     if (!dm || !out) return fail(HELM_EINVAL, "fwi_gn_hessvec: bad arguments");
     return born_entry("fwi_gn_hessvec", ops, nfreq, src_idx, nsrc, rec_idx, nrec, dm, nullptr, nullptr, out, tol, opt,
                       iters, stream);
+}
+
+extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                         const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
+                         float* x_out, double* resnorms, void* stream) {
+    const char* name = "fwi_gn_cg";
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !b || !x_out || cg_iters < 0)
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    if (!(damping >= 0) || !std::isfinite(damping)) return fail(HELM_EINVAL, "%s: damping must be >= 0", name);
+    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    if (rc) return rc;
+    helm_solve_opts o;
+    if ((rc = solve_opts(opt, name, &o))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const long N = ops[0]->n();
+    Owned own;
+    int* src_d = own.get<int>(nsrc);
+    int* rec_d = own.get<int>(nrec);
+    double* x = own.get<double>(N);
+    double* r = own.get<double>(N);
+    double* p = own.get<double>(N);
+    double* ap = own.get<double>(N);
+    float* pf = own.get<float>(N);
+    float* hp = own.get<float>(N);
+    double* part = own.get<double>(CG_BLOCKS);
+    if (!src_d || !rec_d || !x || !r || !p || !ap || !pf || !hp || !part)
+        return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    BornWork W;
+    if ((rc = born_alloc(own, N, nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
+    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+
+    std::vector<double> hpart(CG_BLOCKS);
+    auto dot = [&](const double* a, const double* c, double* result) -> int {
+        hipLaunchKernelGGL(k_cg_dot, dim3(CG_BLOCKS), dim3(256), 0, s, a, c, N, part);
+        HELM_CHECK_LAUNCH();
+        HELM_HIP(hipMemcpyAsync(hpart.data(), part, sizeof(double) * CG_BLOCKS, hipMemcpyDeviceToHost, s));
+        HELM_HIP(hipStreamSynchronize(s));
+        double acc = 0;
+        for (int i = 0; i < CG_BLOCKS; ++i) acc += hpart[i];
+        *result = acc;
+        return HELM_OK;
+    };
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    HELM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    hipLaunchKernelGGL(k_f2d, dim3(nb), dim3(256), 0, s, b, N, r);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipMemcpyAsync(p, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    double rr;
+    if ((rc = dot(r, r, &rr))) return rc;
+    if (resnorms) resnorms[0] = std::sqrt(rr);
+    int worst = HELM_OK;
+    for (int k = 0; k < cg_iters; ++k) {
+        if (rr == 0) {   // b = 0 or an exact solution: the remaining steps change nothing
+            if (resnorms)
+                for (int q = k + 1; q <= cg_iters; ++q) resnorms[q] = 0;
+            break;
+        }
+        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, p, N, pf);
+        HELM_CHECK_LAUNCH();
+        rc = born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, pf, nullptr, nullptr, hp, tol, o, nullptr, s, W, k > 0);
+        if (rc < 0) return rc;
+        worst = std::max(worst, rc);
+        hipLaunchKernelGGL(k_cg_ap, dim3(nb), dim3(256), 0, s, hp, p, damping, N, ap);
+        HELM_CHECK_LAUNCH();
+        double pap;
+        if ((rc = dot(p, ap, &pap))) return rc;
+        if (!(pap > 0)) return fail(HELM_ENAN, "%s: p.Ap = %g at step %d (the system is not positive definite)",
+                                    name, pap, k);
+        const double alpha = rr / pap;
+        hipLaunchKernelGGL(k_cg_xr, dim3(nb), dim3(256), 0, s, x, r, p, ap, alpha, N);
+        HELM_CHECK_LAUNCH();
+        double rr_new;
+        if ((rc = dot(r, r, &rr_new))) return rc;
+        if (resnorms) resnorms[k + 1] = std::sqrt(rr_new);
+        hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(256), 0, s, p, r, rr_new / rr, N);
+        HELM_CHECK_LAUNCH();
+        rr = rr_new;
+    }
+    hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, x, N, x_out);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipStreamSynchronize(s));
+    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
 }

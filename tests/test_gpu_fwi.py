@@ -218,3 +218,26 @@ def test_born_pair_dot_product_and_gn_quadratic_form(gpu):
     assert abs(quad - nrm2) <= 1e-5 * nrm2
     for o in ops:
         o.close()
+
+
+def test_gn_cg_matches_oracle(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=24, nx=32, nsrc=2, nrec=5)
+    bvec = np.random.default_rng(43).standard_normal(k2.shape).astype(np.float32)
+    damping, steps = 1e-2, 4
+    x_o, n_o = fwi.gn_cg(k2, gamma, omegas, h, src, rec, bvec.astype(np.float64), damping, steps)
+    ops = lin_ops(k2, gamma, omegas, h)
+    print("gauss-newton cg", flush=True)
+    x, norms, code = api.fwi_gn_cg(ops, src, rec, torch.tensor(bvec, device="cuda"), damping=damping,
+                                   cg_iters=steps, tol=1e-10, krylov_dtype="c128")
+    assert code == 0 and norms.shape == (steps + 1,)
+    assert abs(norms[0] - n_o[0]) <= 1e-6 * n_o[0]
+    assert np.allclose(norms, n_o, rtol=1e-4, atol=0)
+    assert relerr(x.cpu().numpy().astype(np.float64), x_o) <= 1e-4
+    # same bits again, and b = 0 gives x = 0 without solves
+    x2, norms2, _ = api.fwi_gn_cg(ops, src, rec, torch.tensor(bvec, device="cuda"), damping=damping,
+                                  cg_iters=steps, tol=1e-10, krylov_dtype="c128")
+    assert torch.equal(x, x2) and np.array_equal(norms, norms2)
+    z, nz_, codez = api.fwi_gn_cg(ops, src, rec, torch.zeros_like(torch.tensor(bvec, device="cuda")), cg_iters=3)
+    assert codez == 0 and float(z.abs().max()) == 0.0 and np.all(nz_ == 0)
+    for o in ops:
+        o.close()
