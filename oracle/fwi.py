@@ -32,7 +32,10 @@ factor 1/p.
 Gauss-Newton (eq. 3.9-3.11): the Hessian of the misfit without its
 second-order term, applied to a model perturbation, is Re(J^H J dm), with
 J dm from born and Re(J^H dd) from born_adjoint.  gn_cg is textbook conjugate
-gradients on the damped system (Re(J^H J) + damping I) x = b built on it.
+gradients on the damped system (Re(J^H J) + damping I) x = b built on it;
+gn_step is one Gauss-Newton step m + mu dm with dm from CG on -grad, and
+frequency_continuation runs Alg. 1 (cycles of sliding frequency windows) with
+those steps.
 
 All solves are SuperLU factorisations in complex128.
 """
@@ -185,3 +188,31 @@ def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=Non
         p = r + (rr_new / rr) * p
         rr = rr_new
     return x, np.array(norms)
+
+
+def gn_step(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, damping, cg_iters, mu, hz=None):
+    """One Gauss-Newton step (Sec. 3.3): Phi and grad at m, dm from cg_iters CG
+    steps on (Re(J^H J) + damping I) dm = -grad, and m + mu dm.  Returns
+    (m_new, Phi(m), CG residual norms)."""
+    phi, g = misfit_and_grad(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, hz)
+    dm, norms = gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, -g, damping, cg_iters, hz)
+    return kappa2 + mu * dm, phi, norms
+
+
+def frequency_continuation(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, cycles, window, gn_iters, damping,
+                           cg_iters, mu, hz=None):
+    """Alg. 1: for each cycle (i_start, i_end) (0-based, inclusive) and each
+    i in it, gn_iters Gauss-Newton steps on the data of the frequencies
+    omega_max(i - window, 0) .. omega_i, each cycle starting from the previous
+    model.  dobs [nf][ns][nrec] for all frequencies; gamma is fixed.  Returns
+    the final model and the misfit before every step."""
+    m = np.asarray(kappa2, np.float64)
+    history = []
+    for i0, i1 in cycles:
+        for i in range(i0, i1 + 1):
+            lo = max(i - window, 0)
+            for _ in range(gn_iters):
+                m, phi, _ = gn_step(m, gamma, omegas[lo:i + 1], hx, src_idx, rec_idx, dobs[lo:i + 1], damping,
+                                    cg_iters, mu, hz)
+                history.append(phi)
+    return m, np.array(history)
