@@ -307,6 +307,24 @@ int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, con
               double* resnorms, void* stream);
 
 /*
+ * fwi_gn_step -- one Gauss-Newton step of the inversion (Sec. 3.3): the misfit
+ * and gradient at m (as fwi_misfit_grad), dm from cg_iters conjugate-gradient
+ * steps on (Re(J^H J) + damping I) dm = -grad (as fwi_gn_cg), and
+ * m_new = m + mu dm.  One step of a window of Alg. 1 (frequency continuation).
+ *   m: float [nz][nx] (device), the model the operators were set up with (the
+ *     caller keeps them consistent); m_new (device) may alias m;
+ *   dobs: c64 [nfreq][nsrc][nrec] (device); misfit (host): Phi(m);
+ *   grad (device, float [nz][nx]): dPhi/dm at m; resnorms (host, may be NULL):
+ *     [cg_iters + 1] CG residual norms.
+ * The CG recomputes the point-source fields once (one forward batch more than
+ * strictly needed).  Returns as fwi_born; EINVAL for a non-finite mu.
+ */
+int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                const void* dobs, const float* m, double damping, int cg_iters, double mu, double tol,
+                const helm_solve_opts* opt, float* m_new, double* misfit, float* grad, double* resnorms,
+                void* stream);
+
+/*
  * helm_autotune -- kernel selection for the network's convolutions.  With
  * autotuning on (the default), the first eager launch of each convolution shape
  * times every applicable kernel (halo-tiled persistent with 16 or 32 output

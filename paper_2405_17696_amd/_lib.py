@@ -102,6 +102,10 @@ SIGNATURES = {
     "fwi_gn_cg": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.c_int,
                             C.c_void_p, C.c_double, C.c_int, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
                             C.POINTER(C.c_double), C.c_void_p]),
+    "fwi_gn_step": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int),
+                              C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
+                              C.POINTER(SolveOpts), C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
+                              C.POINTER(C.c_double), C.c_void_p]),
     "cnn_precond_train": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(TrainOpts), C.c_uint64,
                                     C.POINTER(C.c_float), C.c_void_p]),
     "cnn_layer_forward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 5 + [C.c_int, C.c_void_p]),

@@ -488,6 +488,40 @@ def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_i
     return x, np.array(norms[:], dtype=np.float64), code
 
 
+def fwi_gn_step(ops, src_idx, rec_idx, dobs: torch.Tensor, m: torch.Tensor, damping: float, cg_iters: int,
+                mu: float = 1.0, tol: float = 1e-6, precond: str = "mg", restart: int = 0, maxit: int = 300,
+                krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None,
+                m_new: torch.Tensor | None = None):
+    """One Gauss-Newton step m + mu dm, dm from CG on (Re(J^H J) + damping I) dm =
+    -grad; ops must be set up with m.  Returns (m_new, misfit at m, grad,
+    CG residual norms, code)."""
+    import numpy as np
+    lib = L.load()
+    if isinstance(ops, HelmOp):
+        ops = [ops]
+    src = [int(v) for v in np.asarray(src_idx).ravel()]
+    rec = [int(v) for v in np.asarray(rec_idx).ravel()]
+    nf, ns, nr = len(ops), len(src), len(rec)
+    if dobs.dtype != torch.complex64 or tuple(dobs.shape) != (nf, ns, nr):
+        raise ValueError(f"dobs must be complex64 of shape {(nf, ns, nr)}")
+    if m.dtype != torch.float32 or m.numel() != ops[0].n:
+        raise ValueError("m must be float32 [nz][nx]")
+    dobs, m = dobs.contiguous(), m.contiguous()
+    m_new = torch.empty_like(m) if m_new is None else m_new
+    grad = torch.empty_like(m)
+    handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
+                    L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+    phi = C.c_double()
+    norms = (C.c_double * (cg_iters + 1))()
+    code = lib.fwi_gn_step(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(dobs), _ptr(m),
+                           float(damping), int(cg_iters), float(mu), float(tol), C.byref(o), _ptr(m_new),
+                           C.byref(phi), _ptr(grad), norms, _stream())
+    L.check(code, soft_ok=True)
+    return m_new, phi.value, grad, np.array(norms[:], dtype=np.float64), code
+
+
 class FwiMisfit(torch.autograd.Function):
     """Phi(m) = 1/2 sum_{f,s} |R H_f(m)^{-1} g_s - d_fs|^2 as a differentiable function
     of the squared slowness m (float32 [nz][nx] on the GPU).  The forward pass runs

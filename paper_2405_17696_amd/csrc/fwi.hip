@@ -159,9 +159,15 @@ __global__ __launch_bounds__(256) void k_cg_dot(const double* __restrict__ a, co
     if (tid == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_f2d(const float* __restrict__ a, long n, double* __restrict__ b) {
+__global__ void k_f2d_scaled(const float* __restrict__ a, double sign, long n, double* __restrict__ b) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) b[t] = (double)a[t];
+    if (t < n) b[t] = sign * (double)a[t];
+}
+
+// m_new = m + mu dm (FP32 model arrays; m_new may alias m)
+__global__ void k_model_update(const float* m, const float* __restrict__ dm, double mu, long n, float* m_new) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) m_new[t] = (float)((double)m[t] + mu * (double)dm[t]);
 }
 
 // ap = hp + damping p
@@ -510,23 +516,14 @@ extern "C" int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_id
                       iters, stream);
 }
 
-extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
-                         const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
-                         float* x_out, double* resnorms, void* stream) {
-    const char* name = "fwi_gn_cg";
-    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !b || !x_out || cg_iters < 0)
-        return fail(HELM_EINVAL, "%s: bad arguments", name);
-    if (!(damping >= 0) || !std::isfinite(damping)) return fail(HELM_EINVAL, "%s: damping must be >= 0", name);
-    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
-    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
-    if (rc) return rc;
-    helm_solve_opts o;
-    if ((rc = solve_opts(opt, name, &o))) return rc;
-    hipStream_t s = (hipStream_t)stream;
+// cg_iters CG steps from x = 0 on (Re(J^H J) + damping I) x = sign * b (b float
+// [N], device) into x_out (float, device); FP64 vector work, dot products
+// folded in a fixed order; the point-source fields are computed on the first
+// product and reused.
+static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d,
+                      int nrec, const float* b, double sign, double damping, int cg_iters, double tol,
+                      const helm_solve_opts& o, float* x_out, double* resnorms, hipStream_t s, Owned& own) {
     const long N = ops[0]->n();
-    Owned own;
-    int* src_d = own.get<int>(nsrc);
-    int* rec_d = own.get<int>(nrec);
     double* x = own.get<double>(N);
     double* r = own.get<double>(N);
     double* p = own.get<double>(N);
@@ -534,13 +531,10 @@ extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, in
     float* pf = own.get<float>(N);
     float* hp = own.get<float>(N);
     double* part = own.get<double>(CG_BLOCKS);
-    if (!src_d || !rec_d || !x || !r || !p || !ap || !pf || !hp || !part)
-        return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    if (!x || !r || !p || !ap || !pf || !hp || !part) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     BornWork W;
+    int rc;
     if ((rc = born_alloc(own, N, nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
-    HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
-    HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
-
     std::vector<double> hpart(CG_BLOCKS);
     auto dot = [&](const double* a, const double* c, double* result) -> int {
         hipLaunchKernelGGL(k_cg_dot, dim3(CG_BLOCKS), dim3(256), 0, s, a, c, N, part);
@@ -554,7 +548,7 @@ extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, in
     };
     const unsigned nb = (unsigned)((N + 255) / 256);
     HELM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
-    hipLaunchKernelGGL(k_f2d, dim3(nb), dim3(256), 0, s, b, N, r);
+    hipLaunchKernelGGL(k_f2d_scaled, dim3(nb), dim3(256), 0, s, b, sign, N, r);
     HELM_CHECK_LAUNCH();
     HELM_HIP(hipMemcpyAsync(p, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     double rr;
@@ -589,6 +583,80 @@ extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, in
         rr = rr_new;
     }
     hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, x, N, x_out);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipStreamSynchronize(s));
+    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}
+
+// Shared argument checks and source/receiver upload of the Gauss-Newton entry points.
+static int gn_setup(const char* name, const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
+                    const int* rec_idx, int nrec, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
+                    helm_solve_opts* o, int** src_d, int** rec_d, hipStream_t s, Owned& own) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || cg_iters < 0)
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    if (!(damping >= 0) || !std::isfinite(damping)) return fail(HELM_EINVAL, "%s: damping must be >= 0", name);
+    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    if (rc) return rc;
+    if ((rc = solve_opts(opt, name, o))) return rc;
+    *src_d = own.get<int>(nsrc);
+    *rec_d = own.get<int>(nrec);
+    if (!*src_d || !*rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    HELM_HIP(hipMemcpyAsync(*src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
+    HELM_HIP(hipMemcpyAsync(*rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
+    return HELM_OK;
+}
+
+extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+                         const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
+                         float* x_out, double* resnorms, void* stream) {
+    const char* name = "fwi_gn_cg";
+    if (!b || !x_out) return fail(HELM_EINVAL, "%s: bad arguments", name);
+    hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    helm_solve_opts o;
+    int *src_d = nullptr, *rec_d = nullptr;
+    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, damping, cg_iters, tol, opt, &o, &src_d, &rec_d,
+                      s, own);
+    if (rc) return rc;
+    return gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, b, 1.0, damping, cg_iters, tol, o, x_out, resnorms,
+                      s, own);
+}
+
+extern "C" int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
+                           int nrec, const void* dobs, const float* m, double damping, int cg_iters, double mu,
+                           double tol, const helm_solve_opts* opt, float* m_new, double* misfit, float* grad,
+                           double* resnorms, void* stream) {
+    const char* name = "fwi_gn_step";
+    if (!dobs || !m || !m_new || !misfit || !grad || !std::isfinite(mu))
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    helm_solve_opts o;
+    int *src_d = nullptr, *rec_d = nullptr;
+    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, damping, cg_iters, tol, opt, &o, &src_d, &rec_d,
+                      s, own);
+    if (rc) return rc;
+    const long N = ops[0]->n();
+    const int nfs = nfreq * nsrc;
+    // misfit and gradient at m (the operators' model)
+    c64* rhs = own.get<c64>((size_t)nfs * N);
+    float* dm = own.get<float>(N);
+    if (!rhs || !dm) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
+    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
+    HELM_CHECK_LAUNCH();
+    rc = misfit_grad_core(ops, nfreq, nsrc, rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, nullptr, s,
+                          own);
+    if (rc < 0) return rc;
+    int worst = rc;
+    // dm from CG on -grad, then m_new = m + mu dm
+    rc = gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, grad, -1.0, damping, cg_iters, tol, o, dm, resnorms, s,
+                    own);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+    hipLaunchKernelGGL(k_model_update, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, m, dm, mu, N, m_new);
     HELM_CHECK_LAUNCH();
     HELM_HIP(hipStreamSynchronize(s));
     return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;

@@ -241,3 +241,39 @@ def test_gn_cg_matches_oracle(gpu):
     assert codez == 0 and float(z.abs().max()) == 0.0 and np.all(nz_ == 0)
     for o in ops:
         o.close()
+
+
+def test_gn_step_matches_oracle(gpu):
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=24, nx=32, nsrc=3, nrec=8)
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    damping, steps, mu = 1e-3, 3, 0.8
+    m_o, phi_o, norms_o = fwi.gn_step(k2, gamma, omegas, h, src, rec, dobs, damping, steps, mu)
+    ops = lin_ops(k2, gamma, omegas, h)
+    print("gauss-newton step", flush=True)
+    m = torch.tensor(k2, dtype=torch.float32, device="cuda")
+    m_new, phi, grad, norms, code = api.fwi_gn_step(ops, src, rec, torch.tensor(dobs, dtype=torch.complex64,
+                                                                                 device="cuda"),
+                                                    m, damping, steps, mu=mu, tol=1e-10, krylov_dtype="c128")
+    assert code == 0
+    assert abs(phi - phi_o) <= 1e-6 * phi_o
+    assert np.allclose(norms, norms_o, rtol=1e-4, atol=0)
+    step = m_new.cpu().numpy().astype(np.float64) - k2
+    assert relerr(step, m_o - k2) <= 1e-4
+    for o in ops:
+        o.close()
+
+
+def test_frequency_continuation_matches_oracle(gpu):
+    from paper_2405_17696_amd import inversion
+    k2, gamma, omegas, h, src, rec, dobs = problem(nz=24, nx=32, nsrc=3, nrec=8, freqs=(16.0, 12.0, 10.0))
+    dobs = dobs.astype(np.complex64).astype(np.complex128)
+    kw = dict(cycles=[(0, 2)], window=1, gn_iters=1, damping=1e-3, cg_iters=3, mu=1.0)
+    m_o, hist_o = fwi.frequency_continuation(k2, gamma, omegas, h, src, rec, dobs, **kw)
+    print("frequency continuation", flush=True)
+    m, hist = inversion.frequency_continuation(
+        torch.tensor(k2, dtype=torch.float32, device="cuda"), torch.tensor(gamma, dtype=torch.float32, device="cuda"),
+        omegas, h, src, rec, torch.tensor(dobs, dtype=torch.complex64, device="cuda"), tol=1e-10,
+        krylov_dtype="c128", **kw)
+    assert [w for w, _, _ in hist] == [(0, 0), (0, 1), (1, 2)]
+    assert np.allclose([p for _, p, _ in hist], hist_o, rtol=1e-5, atol=0)
+    assert relerr(m.cpu().numpy().astype(np.float64) - k2, m_o - k2) <= 1e-4
