@@ -316,8 +316,8 @@ int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, con
  *   dobs: c64 [nfreq][nsrc][nrec] (device); misfit (host): Phi(m);
  *   grad (device, float [nz][nx]): dPhi/dm at m; resnorms (host, may be NULL):
  *     [cg_iters + 1] CG residual norms.
- * The CG recomputes the point-source fields once (one forward batch more than
- * strictly needed).  Returns as fwi_born; EINVAL for a non-finite mu.
+ * The CG reuses the gradient's point-source fields: a step costs 2 + 2 cg_iters
+ * solve batches.  Returns as fwi_born; EINVAL for a non-finite mu.
  */
 int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
                 const void* dobs, const float* m, double damping, int cg_iters, double mu, double tol,

@@ -238,10 +238,10 @@ static int check_args(const char* name, const helm_op_t* ops, int nfreq, const i
 // residuals and misfit, adjoint solves, gradient; misfit and gradient times scale.
 static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs, const c64* dobs_d,
                             const int* rec_d, int nrec, double tol, helm_solve_opts o, double scale, double* misfit,
-                            float* grad, int* iters, hipStream_t s, Owned& own) {
+                            float* grad, int* iters, hipStream_t s, Owned& own, c128* u_keep = nullptr) {
     const long N = ops[0]->n();
     const int nfs = nfreq * nper;
-    c128* u = own.get<c128>((size_t)nfs * N);
+    c128* u = u_keep ? u_keep : own.get<c128>((size_t)nfs * N);   // u_keep: the caller keeps the fields
     c128* lam = own.get<c128>((size_t)nfs * N);
     double* gacc = own.get<double>(N);
     double* part = own.get<double>(nfs);
@@ -522,7 +522,8 @@ extern "C" int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_id
 // product and reused.
 static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d,
                       int nrec, const float* b, double sign, double damping, int cg_iters, double tol,
-                      const helm_solve_opts& o, float* x_out, double* resnorms, hipStream_t s, Owned& own) {
+                      const helm_solve_opts& o, float* x_out, double* resnorms, hipStream_t s, Owned& own,
+                      const BornWork* fields = nullptr) {
     const long N = ops[0]->n();
     double* x = own.get<double>(N);
     double* r = own.get<double>(N);
@@ -534,7 +535,10 @@ static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsr
     if (!x || !r || !p || !ap || !pf || !hp || !part) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     BornWork W;
     int rc;
-    if ((rc = born_alloc(own, N, nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
+    if (fields)
+        W = *fields;   // the point-source fields are already in W.u
+    else if ((rc = born_alloc(own, N, nfreq * nsrc, (long)nfreq * nsrc * nrec, W)))
+        return rc;
     std::vector<double> hpart(CG_BLOCKS);
     auto dot = [&](const double* a, const double* c, double* result) -> int {
         hipLaunchKernelGGL(k_cg_dot, dim3(CG_BLOCKS), dim3(256), 0, s, a, c, N, part);
@@ -563,7 +567,8 @@ static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsr
         }
         hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, p, N, pf);
         HELM_CHECK_LAUNCH();
-        rc = born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, pf, nullptr, nullptr, hp, tol, o, nullptr, s, W, k > 0);
+        rc = born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, pf, nullptr, nullptr, hp, tol, o, nullptr, s, W,
+                       fields != nullptr || k > 0);
         if (rc < 0) return rc;
         worst = std::max(worst, rc);
         hipLaunchKernelGGL(k_cg_ap, dim3(nb), dim3(256), 0, s, hp, p, damping, N, ap);
@@ -640,20 +645,22 @@ extern "C" int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, 
     const long N = ops[0]->n();
     const int nfs = nfreq * nsrc;
     // misfit and gradient at m (the operators' model)
-    c64* rhs = own.get<c64>((size_t)nfs * N);
+    BornWork W;
+    if ((rc = born_alloc(own, N, nfs, (long)nfs * nrec, W))) return rc;
     float* dm = own.get<float>(N);
-    if (!rhs || !dm) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
-    HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
+    if (!dm) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    HELM_HIP(hipMemsetAsync(W.rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
     const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
-    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
+    hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, W.rhs);
     HELM_CHECK_LAUNCH();
-    rc = misfit_grad_core(ops, nfreq, nsrc, rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, nullptr, s,
-                          own);
+    // the gradient's forward solves leave the point-source fields in W.u for the CG
+    rc = misfit_grad_core(ops, nfreq, nsrc, W.rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, nullptr,
+                          s, own, W.u);
     if (rc < 0) return rc;
     int worst = rc;
     // dm from CG on -grad, then m_new = m + mu dm
     rc = gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, grad, -1.0, damping, cg_iters, tol, o, dm, resnorms, s,
-                    own);
+                    own, &W);
     if (rc < 0) return rc;
     worst = std::max(worst, rc);
     hipLaunchKernelGGL(k_model_update, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, m, dm, mu, N, m_new);
