@@ -37,6 +37,15 @@ gn_step is one Gauss-Newton step m + mu dm with dm from CG on -grad, and
 frequency_continuation runs Alg. 1 (cycles of sliding frequency windows) with
 those steps.
 
+Regularisation (Sec. 5, eq. 5.1 and 5.2): the objective gains alpha R(m) with
+    R_high(m) = || Lap_h (m - m_ref) ||_2^2,   R_diff(m) = || grad_h (m - m_ref) ||_2^2,
+grad_h the forward differences between neighbouring nodes of the nodal grid
+and Lap_h = -grad_h^T grad_h its divergence (so both terms vanish on constant
+m - m_ref; sums over nodes and edges, no cell-area factor).  Their gradients are
+2 Lap_h^2 (m - m_ref) and 2 grad_h^T grad_h (m - m_ref), their Hessians 2 Lap_h^2
+and 2 grad_h^T grad_h, the alpha nabla^2 R term of the Gauss-Newton matrix of
+eq. 3.11.
+
 All solves are SuperLU factorisations in complex128.
 """
 from __future__ import annotations
@@ -167,11 +176,66 @@ def gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, dm, hz=None):
     return born_adjoint(kappa2, gamma, omegas, hx, src_idx, rec_idx, jdm, hz)
 
 
-def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=None):
-    """Conjugate gradients on the damped Gauss-Newton system (Re(J^H J) + damping I) x = b
-    from x = 0 (the inner solve of a Gauss-Newton step, Sec. 3.3), `iters` steps.
+def nodal_grad(d, hx, hz):
+    """Forward differences between neighbouring nodes: (gx [nz][nx-1], gz [nz-1][nx])."""
+    d = np.asarray(d, np.float64)
+    return (d[:, 1:] - d[:, :-1]) / hx, (d[1:, :] - d[:-1, :]) / hz
+
+
+def nodal_grad_T(gx, gz, hx, hz):
+    """Adjoint of nodal_grad: an edge difference (b - a)/h sends -1/h to a and +1/h to b."""
+    nz, nx = gz.shape[0] + 1, gx.shape[1] + 1
+    out = np.zeros((nz, nx))
+    out[:, 1:] += gx / hx
+    out[:, :-1] -= gx / hx
+    out[1:, :] += gz / hz
+    out[:-1, :] -= gz / hz
+    return out
+
+
+def reg_laplacian(d, hx, hz):
+    """Lap_h d = -grad_h^T grad_h d (the 5-point Laplacian with the nodal-gradient closure)."""
+    return -nodal_grad_T(*nodal_grad(d, hx, hz), hx, hz)
+
+
+REG_NONE, REG_HIGH, REG_DIFF = 0, 1, 2
+
+
+def regulariser(kind, m, m_ref, hx, hz=None):
+    """(R(m), dR/dm) of eq. 5.1 (kind REG_HIGH) or eq. 5.2 (REG_DIFF); REG_NONE gives zeros."""
+    hz = hx if hz is None else hz
+    d = np.asarray(m, np.float64) - np.asarray(m_ref, np.float64)
+    if kind == REG_NONE:
+        return 0.0, np.zeros_like(d)
+    if kind == REG_HIGH:
+        ld = reg_laplacian(d, hx, hz)
+        return float(np.sum(ld * ld)), 2.0 * reg_laplacian(ld, hx, hz)
+    if kind == REG_DIFF:
+        gx, gz = nodal_grad(d, hx, hz)
+        return float(np.sum(gx * gx) + np.sum(gz * gz)), 2.0 * nodal_grad_T(gx, gz, hx, hz)
+    raise ValueError(kind)
+
+
+def reg_hessvec(kind, v, hx, hz=None):
+    """nabla^2 R applied to v (R is quadratic: 2 Lap_h^2 v or 2 grad_h^T grad_h v)."""
+    hz = hx if hz is None else hz
+    if kind == REG_NONE:
+        return np.zeros_like(np.asarray(v, np.float64))
+    if kind == REG_HIGH:
+        return 2.0 * reg_laplacian(reg_laplacian(v, hx, hz), hx, hz)
+    if kind == REG_DIFF:
+        return 2.0 * nodal_grad_T(*nodal_grad(v, hx, hz), hx, hz)
+    raise ValueError(kind)
+
+
+def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=None, reg=REG_NONE, alpha=0.0):
+    """Conjugate gradients on the damped Gauss-Newton system
+    (Re(J^H J) + alpha nabla^2 R + damping I) x = b from x = 0 (the inner solve of
+    a Gauss-Newton step, Sec. 3.3, eq. 3.11), `iters` steps.
     Returns x (float64 [nz][nx]) and the residual norms ||b - A x_k||, k = 0..iters."""
-    A = lambda v: gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, v, hz) + damping * v
+    hz_ = hx if hz is None else hz
+    A = lambda v: (gn_hessvec(kappa2, gamma, omegas, hx, src_idx, rec_idx, v, hz) + damping * v
+                   + alpha * reg_hessvec(reg, v, hx, hz_))
     b = np.asarray(b, np.float64)
     x = np.zeros_like(b)
     r = b.copy()
@@ -180,9 +244,9 @@ def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=Non
     norms = [np.sqrt(rr)]
     for _ in range(iters):
         ap = A(p)
-        alpha = rr / float(np.sum(p * ap))
-        x = x + alpha * p
-        r = r - alpha * ap
+        step = rr / float(np.sum(p * ap))
+        x = x + step * p
+        r = r - step * ap
         rr_new = float(np.sum(r * r))
         norms.append(np.sqrt(rr_new))
         p = r + (rr_new / rr) * p
@@ -190,29 +254,37 @@ def gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, b, damping, iters, hz=Non
     return x, np.array(norms)
 
 
-def gn_step(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, damping, cg_iters, mu, hz=None):
-    """One Gauss-Newton step (Sec. 3.3): Phi and grad at m, dm from cg_iters CG
-    steps on (Re(J^H J) + damping I) dm = -grad, and m + mu dm.  Returns
-    (m_new, Phi(m), CG residual norms)."""
+def gn_step(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, damping, cg_iters, mu, hz=None, reg=REG_NONE,
+            alpha=0.0, m_ref=None):
+    """One Gauss-Newton step (Sec. 3.3) on Phi(m) + alpha R(m): the data misfit
+    Phi and the gradient g = dPhi/dm + alpha dR/dm at m, dm from cg_iters CG
+    steps on (Re(J^H J) + alpha nabla^2 R + damping I) dm = -g, and m + mu dm.
+    Returns (m_new, Phi(m), CG residual norms, R(m), g)."""
     phi, g = misfit_and_grad(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, hz)
-    dm, norms = gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, -g, damping, cg_iters, hz)
-    return kappa2 + mu * dm, phi, norms
+    rv = 0.0
+    if reg != REG_NONE:
+        rv, rg = regulariser(reg, kappa2, m_ref, hx, hz)
+        g = g + alpha * rg
+    dm, norms = gn_cg(kappa2, gamma, omegas, hx, src_idx, rec_idx, -g, damping, cg_iters, hz, reg, alpha)
+    return kappa2 + mu * dm, phi, norms, rv, g
 
 
 def frequency_continuation(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, cycles, window, gn_iters, damping,
-                           cg_iters, mu, hz=None):
+                           cg_iters, mu, hz=None, reg=REG_NONE, alpha=0.0, m_ref=None):
     """Alg. 1: for each cycle (i_start, i_end) (0-based, inclusive) and each
     i in it, gn_iters Gauss-Newton steps on the data of the frequencies
     omega_max(i - window, 0) .. omega_i, each cycle starting from the previous
-    model.  dobs [nf][ns][nrec] for all frequencies; gamma is fixed.  Returns
-    the final model and the misfit before every step."""
+    model.  dobs [nf][ns][nrec] for all frequencies; gamma is fixed; the
+    regulariser (reg, alpha) keeps its reference model m_ref (default: the
+    initial model) fixed.  Returns the final model and the misfit before every step."""
     m = np.asarray(kappa2, np.float64)
+    m_ref = m.copy() if m_ref is None else np.asarray(m_ref, np.float64)
     history = []
     for i0, i1 in cycles:
         for i in range(i0, i1 + 1):
             lo = max(i - window, 0)
             for _ in range(gn_iters):
-                m, phi, _ = gn_step(m, gamma, omegas[lo:i + 1], hx, src_idx, rec_idx, dobs[lo:i + 1], damping,
-                                    cg_iters, mu, hz)
+                m, phi, _, _, _ = gn_step(m, gamma, omegas[lo:i + 1], hx, src_idx, rec_idx, dobs[lo:i + 1], damping,
+                                          cg_iters, mu, hz, reg, alpha, m_ref)
                 history.append(phi)
     return m, np.array(history)

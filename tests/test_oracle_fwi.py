@@ -202,3 +202,130 @@ def test_gauss_newton_frequency_continuation_reduces_misfit_and_model_error():
     for w in range(3):                      # two steps per window: the second starts lower
         assert hist[2 * w + 1] < hist[2 * w]
     assert np.linalg.norm(m - kt) < np.linalg.norm(k2 - kt)
+
+
+# ---------------------------------------------------------------- regularisers (eq. 5.1, 5.2)
+def _grad_matrix(nz, nx, hx, hz):
+    """The nodal-grid gradient as an explicit matrix, one row per edge, built
+    entry by entry: x-edges (i, k)-(i, k+1) first, then z-edges (i, k)-(i+1, k)."""
+    rows = []
+    for i in range(nz):
+        for k in range(nx - 1):
+            r = np.zeros(nz * nx)
+            r[i * nx + k + 1] = 1.0 / hx
+            r[i * nx + k] = -1.0 / hx
+            rows.append(r)
+    for i in range(nz - 1):
+        for k in range(nx):
+            r = np.zeros(nz * nx)
+            r[(i + 1) * nx + k] = 1.0 / hz
+            r[i * nx + k] = -1.0 / hz
+            rows.append(r)
+    return np.array(rows)
+
+
+def test_regularisers_brute_force_matrices():
+    nz, nx, hx, hz = 4, 5, 0.7, 1.3
+    rng = np.random.default_rng(40)
+    m, mref = rng.standard_normal((nz, nx)), rng.standard_normal((nz, nx))
+    G = _grad_matrix(nz, nx, hx, hz)
+    Lap = -G.T @ G
+    d = (m - mref).ravel()
+    r_diff, g_diff = fwi.regulariser(fwi.REG_DIFF, m, mref, hx, hz)
+    r_high, g_high = fwi.regulariser(fwi.REG_HIGH, m, mref, hx, hz)
+    assert abs(r_diff - np.sum((G @ d) ** 2)) <= 1e-12 * r_diff
+    assert abs(r_high - np.sum((Lap @ d) ** 2)) <= 1e-12 * r_high
+    assert np.allclose(g_diff.ravel(), 2 * G.T @ G @ d, rtol=1e-12, atol=1e-12 * np.abs(g_diff).max())
+    assert np.allclose(g_high.ravel(), 2 * Lap.T @ Lap @ d, rtol=1e-12, atol=1e-12 * np.abs(g_high).max())
+    v = rng.standard_normal((nz, nx))
+    assert np.allclose(fwi.reg_hessvec(fwi.REG_DIFF, v, hx, hz).ravel(), 2 * G.T @ G @ v.ravel(), atol=1e-10)
+    assert np.allclose(fwi.reg_hessvec(fwi.REG_HIGH, v, hx, hz).ravel(), 2 * Lap @ Lap @ v.ravel(), atol=1e-8)
+    # interior rows of Lap are the 5-point stencil (sum of neighbours - 4 u over h^2 for hx = hz)
+    i, k = 2, 2
+    row = Lap[i * nx + k].reshape(nz, nx)
+    assert abs(row[i, k] + 2 / hx ** 2 + 2 / hz ** 2) < 1e-12
+    assert abs(row[i, k - 1] - 1 / hx ** 2) < 1e-12 and abs(row[i - 1, k] - 1 / hz ** 2) < 1e-12
+
+
+def test_regularisers_closed_forms():
+    """A linear ramp has constant differences (R_diff closed form, R_high = 0
+    in the interior rows ... and everywhere, since the ends see one-sided
+    constant differences that cancel); a product of cosine modes
+    cos(pi q (k + 1/2) / nx) cos(pi p (i + 1/2) / nz) is an eigenvector of the
+    nodal Laplacian with eigenvalue -lam, lam = 4/hx^2 sin^2(pi q / 2nx) +
+    4/hz^2 sin^2(pi p / 2nz), so R_diff = lam ||d||^2 and R_high = lam^2 ||d||^2;
+    constants cost nothing."""
+    nz, nx, hx, hz = 9, 12, 0.5, 0.8
+    i = np.arange(nz)[:, None] * np.ones((1, nx))
+    k = np.arange(nx)[None, :] * np.ones((nz, 1))
+    a, b = 0.3, -0.7
+    ramp = a * k * hx + b * i * hz
+    r, _ = fwi.regulariser(fwi.REG_DIFF, ramp, 0 * ramp, hx, hz)
+    assert abs(r - (a * a * nz * (nx - 1) + b * b * (nz - 1) * nx)) <= 1e-12 * r
+    for p, q in ((1, 1), (3, 5), (nz - 1, nx - 1), (0, 4)):
+        d = np.cos(np.pi * q * (k + 0.5) / nx) * np.cos(np.pi * p * (i + 0.5) / nz)
+        lam = 4 / hx ** 2 * np.sin(np.pi * q / (2 * nx)) ** 2 + 4 / hz ** 2 * np.sin(np.pi * p / (2 * nz)) ** 2
+        assert np.allclose(fwi.reg_laplacian(d, hx, hz), -lam * d, atol=1e-12 * lam)
+        rd, _ = fwi.regulariser(fwi.REG_DIFF, d + 2.0, 2.0 * np.ones_like(d), hx, hz)
+        rh, _ = fwi.regulariser(fwi.REG_HIGH, d + 2.0, 2.0 * np.ones_like(d), hx, hz)
+        nd = np.sum(d * d)
+        assert abs(rd - lam * nd) <= 1e-10 * lam * nd and abs(rh - lam ** 2 * nd) <= 1e-10 * lam ** 2 * nd
+    for kind in (fwi.REG_HIGH, fwi.REG_DIFF):
+        r, g = fwi.regulariser(kind, np.full((nz, nx), 3.0), np.full((nz, nx), 1.0), hx, hz)
+        assert r == 0.0 and np.all(g == 0)
+
+
+@pytest.mark.parametrize("kind", [fwi.REG_HIGH, fwi.REG_DIFF])
+def test_regulariser_gradient_and_hessian_by_differences(kind):
+    nz, nx, hx, hz = 10, 13, 0.4, 0.6
+    rng = np.random.default_rng(41 + kind)
+    m, mref = rng.standard_normal((nz, nx)), rng.standard_normal((nz, nx))
+    r0, g = fwi.regulariser(kind, m, mref, hx, hz)
+    for t in range(4):
+        v = rng.standard_normal((nz, nx))
+        eps = 1e-4
+        rp, gp = fwi.regulariser(kind, m + eps * v, mref, hx, hz)
+        rm, gm = fwi.regulariser(kind, m - eps * v, mref, hx, hz)
+        fd = (rp - rm) / (2 * eps)
+        assert abs(fd - np.sum(g * v)) <= 1e-7 * abs(fd)
+        hv = fwi.reg_hessvec(kind, v, hx, hz)
+        assert np.allclose((gp - gm) / (2 * eps), hv, rtol=1e-6, atol=1e-6 * np.abs(hv).max())
+        assert np.sum(v * hv) >= 0
+    u, w = rng.standard_normal((nz, nx)), rng.standard_normal((nz, nx))
+    lhs, rhs = np.sum(u * fwi.reg_hessvec(kind, w, hx, hz)), np.sum(w * fwi.reg_hessvec(kind, u, hx, hz))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_regularised_gn_cg_and_step():
+    """The regularised Gauss-Newton matrix (Re(J^H J) + alpha nabla^2 R + damping I)
+    assembled densely: CG reaches its solution; the step's gradient is
+    dPhi/dm + alpha dR/dm (central differences of Phi + alpha R)."""
+    k2, gamma, omegas, h, src, rec, dobs = small_problem(nz=8, nx=8, nsrc=2, nrec=3)
+    n = k2.size
+    damping = 1e-2
+    mref = k2 * (1 + 0.02 * np.random.default_rng(42).standard_normal(k2.shape))
+    # weights that put alpha nabla^2 R on the scale of Re(J^H J) (largest eigenvalue ~70 here)
+    for kind, alpha in ((fwi.REG_HIGH, 1e-8), (fwi.REG_DIFF, 1e-4)):
+        cols = []
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            ej = e.reshape(k2.shape)
+            cols.append((fwi.gn_hessvec(k2, gamma, omegas, h, src, rec, ej)
+                         + alpha * fwi.reg_hessvec(kind, ej, h)).ravel())
+        A = np.array(cols).T + damping * np.eye(n)
+        b = np.random.default_rng(43).standard_normal(k2.shape)
+        x, _ = fwi.gn_cg(k2, gamma, omegas, h, src, rec, b, damping, 3 * n, reg=kind, alpha=alpha)
+        xd = np.linalg.solve(A, b.ravel())
+        assert np.linalg.norm(x.ravel() - xd) <= 1e-6 * np.linalg.norm(xd)
+        m_new, phi, norms, rv, g = fwi.gn_step(k2, gamma, omegas, h, src, rec, dobs, damping, 4, 1.0, reg=kind,
+                                               alpha=alpha, m_ref=mref)
+        obj = lambda m: (fwi.misfit(m, gamma, omegas, h, src, rec, dobs)
+                         + alpha * fwi.regulariser(kind, m, mref, h)[0])
+        v = np.random.default_rng(44).standard_normal(k2.shape) * k2
+        eps = 1e-5
+        fd = (obj(k2 + eps * v) - obj(k2 - eps * v)) / (2 * eps)
+        assert abs(fd - np.sum(g * v)) <= 1e-5 * abs(fd)
+        assert rv == fwi.regulariser(kind, k2, mref, h)[0]
+        # the step is a descent direction of the regularised objective
+        assert np.sum((m_new - k2) * g) < 0

@@ -246,3 +246,105 @@ def test_philox_normal_moments():
     z = philox.complex_normal(200000, (1, 2))
     assert abs(np.mean(np.abs(z) ** 2) - 1.0) < 0.01
     assert abs(np.mean(z)) < 0.01
+
+
+# ---------------------------------------------------------------- shifted Laplacian (eq. 3.12)
+def _sine_spectrum(nz, nx, hx, hz):
+    """Eigenvalues of -Lap_h with Dirichlet-0 ghosts (sine modes), independent of
+    the sparse assembly."""
+    p = np.arange(1, nz + 1)[:, None]
+    q = np.arange(1, nx + 1)[None, :]
+    return ((4 / hz ** 2) * np.sin(np.pi * p / (2 * (nz + 1))) ** 2
+            + (4 / hx ** 2) * np.sin(np.pi * q / (2 * (nx + 1))) ** 2).ravel()
+
+
+@pytest.mark.parametrize("nz,nx,beta", [(12, 14, 0.5), (16, 16, 0.5), (9, 13, 0.3)])
+def test_shifted_laplacian_spectrum_on_circle_in_lower_half_plane(nz, nx, beta):
+    """gamma = 0, constant m: H and P share the sine eigenvectors, so the
+    eigenvalues of P^-1 H are (mu - k^2) / (mu - k^2 + i beta k^2).  They lie on
+    the circle |lambda - 1/2| = 1/2, in the lower half plane for every Laplacian
+    eigenvalue mu > k^2 and in the upper one for mu < k^2.  A sign slip in the
+    shift (1 + beta i) mirrors them into the other half plane."""
+    h = 0.01
+    mus = _sine_spectrum(nz, nx, h, h)
+    # k^2 between two eigenvalues, off the centre of the (symmetric) sine
+    # spectrum, so that the two half planes hold different numbers of modes
+    srt = np.sort(mus)
+    j = int(0.3 * srt.size)
+    k2 = 0.5 * (srt[j] + srt[j + 1])
+    m = 0.4
+    omega = np.sqrt(k2 / m)
+    kap = np.full((nz, nx), m)
+    gam = np.zeros((nz, nx))
+    H = op.assemble(op.helmholtz_coef(kap, gam, omega), h, h).toarray()
+    P = op.assemble(op.shifted_coef(kap, gam, omega, beta=beta), h, h).toarray()
+    lam = np.linalg.eigvals(np.linalg.solve(P, H))
+    assert np.allclose(np.abs(lam - 0.5), 0.5, atol=1e-9)
+    a = mus - omega ** 2 * m
+    b = beta * omega ** 2 * m
+    expect = a / (a + 1j * b)
+    d = np.abs(lam[:, None] - expect[None, :])
+    assert d.min(axis=1).max() < 1e-9 and d.min(axis=0).max() < 1e-9
+    above = a > 1e-9 * np.abs(a).max()
+    below = a < -1e-9 * np.abs(a).max()
+    assert above.sum() > 0 and below.sum() > 0
+    assert np.all(expect[above].imag < 0) and np.all(expect[below].imag > 0)
+    assert (lam.imag < -1e-12).sum() == above.sum()
+    assert (lam.imag > 1e-12).sum() == below.sum()
+
+
+def test_shifted_laplacian_with_constant_gamma_spectrum():
+    """Constant gamma0: the reading P = -Lap - w^2 m (1 - (gamma + beta) i)
+    gives eigenvalues (a + i g0 w^2 m) / (a + i (g0 + beta) w^2 m) of P^-1 H,
+    a = mu - w^2 m; with_gamma=False (the literal no-gamma form) gives
+    (a + i g0 w^2 m) / (a + i beta w^2 m).  A wrong sign or placement of gamma
+    in either operator changes these sets."""
+    nz, nx, h, m, g0, beta = 10, 12, 0.02, 0.25, 0.3, 0.5
+    mus = _sine_spectrum(nz, nx, h, h)
+    srt = np.sort(mus)
+    omega = np.sqrt(0.5 * (srt[40] + srt[41]) / m)
+    kap = np.full((nz, nx), m)
+    gam = np.full((nz, nx), g0)
+    H = op.assemble(op.helmholtz_coef(kap, gam, omega), h, h).toarray()
+    a = mus - omega ** 2 * m
+    k2 = omega ** 2 * m
+    for with_gamma, shift in ((True, g0 + beta), (False, beta)):
+        P = op.assemble(op.shifted_coef(kap, gam, omega, beta=beta, with_gamma=with_gamma), h, h).toarray()
+        lam = np.linalg.eigvals(np.linalg.solve(P, H))
+        expect = (a + 1j * g0 * k2) / (a + 1j * shift * k2)
+        d = np.abs(lam[:, None] - expect[None, :])
+        assert d.min(axis=1).max() < 1e-9 and d.min(axis=0).max() < 1e-9
+
+
+def test_finest_level_is_the_shifted_operator():
+    """Level 0 of the V-cycle applies -Lap_h - diag(shifted_coef) exactly (the
+    far-boundary stencil reduces to the regular one when delta = h)."""
+    med = medium(24, 30, seed=21)
+    hz = 1.3 * med.h
+    V = mg.VCycle(med.kappa2, med.gamma, med.omega, med.h, hz)
+    u = rand_c((3, 24, 30), 5)
+    ref = op.apply(op.shifted_coef(med.kappa2, med.gamma, med.omega), u, med.h, hz)
+    assert relerr(V.levels[0].apply(u), ref) < 1e-14
+    D = op.assemble(op.shifted_coef(med.kappa2, med.gamma, med.omega), med.h, hz).diagonal()
+    assert np.allclose(V.levels[0].diag.ravel(), D, rtol=0, atol=1e-12 * np.abs(D).max())
+
+
+def test_restrict_coef_field_weights():
+    """Normalised full weighting: constants are kept everywhere (including the
+    truncated stencils at the far boundary); interior coarse nodes take the
+    (1/16)[1 2 1; 2 4 2; 1 2 1] average of the 3 x 3 fine nodes around 2I+1;
+    the last coarse row of an even grid renormalises the rows that exist."""
+    rng = np.random.default_rng(3)
+    nz, nx = 10, 9                       # even nz: fine row 2I+2 = 10 is outside for the last I
+    f = rng.uniform(0.2, 1.0, (nz, nx))
+    c = mg.restrict_coef_field(f)
+    assert c.shape == (5, 4)
+    assert np.allclose(mg.restrict_coef_field(np.full((nz, nx), 0.37)), 0.37, atol=1e-15)
+    w = np.array([1.0, 2.0, 1.0])
+    for I, J in ((1, 1), (2, 3), (3, 2)):
+        blk = f[2 * I:2 * I + 3, 2 * J:2 * J + 3]
+        assert abs(c[I, J] - (np.outer(w, w) * blk).sum() / 16) < 1e-14
+    I, J = 4, 1                          # rows 8, 9 exist, row 10 does not
+    blk = f[8:10, 2 * J:2 * J + 3]
+    ww = np.outer(w[:2], w)
+    assert abs(c[I, J] - (ww * blk).sum() / ww.sum()) < 1e-14
