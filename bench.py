@@ -112,6 +112,68 @@ def kernel_roofline(api_lib, name, every):
             "avg_us": avg_ms * 1e3, "achieved": achieved, "work_per_launch": work.value / n.value}
 
 
+def _direct_worker(args):
+    """One host process of the all-core direct baseline: factor H once (SuperLU,
+    the oracle's DirectSolver) and solve its share of the right-hand sides."""
+    k2, g, omega, h, b = args
+    from oracle import operator as op
+    t0 = time.perf_counter()
+    S = op.DirectSolver(op.assemble_helmholtz(k2, g, omega, h))
+    t1 = time.perf_counter()
+    x = S.solve(b)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1, x.shape[0], float(op.relres(op.helmholtz_coef(k2, g, omega), x, b, h, h).max())
+
+
+def cpu_direct_baseline(med, src):
+    """The oracle's sparse direct solve (SuperLU, complex128): factor once per
+    medium and frequency, then solve every right-hand side.  Timed on one core
+    (one process) and on all host cores (one process per core, each factoring
+    once and solving its share, as SuperLU factors on one thread); the
+    processes are started and warmed up before the clock starts."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    k2 = np.asarray(med.kappa2, np.float32).astype(np.float64)
+    g = np.asarray(med.gamma, np.float32).astype(np.float64)
+    b = np.asarray(src, np.complex128)
+    nrhs = b.shape[0]
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fac, sol, _, rr = _direct_worker((k2, g, med.omega, med.h, b))
+        one = time.perf_counter() - t0
+    ncpu = os.cpu_count() or 1
+    nproc = max(1, min(ncpu, 16, nrhs))
+    parts = np.array_split(np.arange(nrhs), nproc)
+    ctx = mp.get_context("spawn")
+    # one BLAS thread per process: SuperLU's dense kernels with a full thread
+    # pool in every process oversubscribe the cores by nproc x and stall
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.update({k: "1" for k in keys})
+    try:
+        with ProcessPoolExecutor(nproc, mp_context=ctx) as ex:
+            warm = b[:1, :8, :8].copy()
+            warm[0, 2, 3] = 1.0
+            list(ex.map(_direct_worker, [(k2[:8, :8], g[:8, :8], med.omega, med.h, warm)] * nproc))
+            t0 = time.perf_counter()
+            res = list(ex.map(_direct_worker, [(k2, g, med.omega, med.h, b[q]) for q in parts]))
+            allc = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"value": nrhs / allc, "unit": "RHS/s", "cores": nproc, "kind": "oracle",
+            "sample": f"all {nrhs} RHS of the 256x256 layered workload, SuperLU complex128 (factor once per "
+                      f"process, then solve), {nproc} processes on {ncpu} host cores, factorisations included",
+            "one_core": {"rhs_per_s": nrhs / one, "factor_s": fac, "solve_ms_per_rhs": 1e3 * sol / nrhs,
+                         "rhs_per_s_after_factor": nrhs / sol, "relres_max": rr},
+            "all_cores": {"seconds": allc, "processes": nproc,
+                          "factor_s_max": max(r[0] for r in res), "relres_max": max(r[3] for r in res)}}
+
+
 def cpu_baseline(med, src, nrhs):
     """The FP64 oracle (MG-preconditioned GMRES(20)) on a bounded sample."""
     try:
@@ -310,7 +372,10 @@ def main_c2(a):
                     "bytes_per_launch": roof["work_per_launch"]}
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(med, src, a.cpu_sample_rhs)
+        # the strong host baseline (direct solve, factor once) is `value`; the
+        # iterative oracle the GPU path mirrors is timed beside it
+        cpu = cpu_direct_baseline(med, src)
+        cpu["mg_gmres_oracle"] = cpu_baseline(med, src, a.cpu_sample_rhs)
     out = {"metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": ("bf16 network / " if precond != "mg" else "") + "c64 Krylov / c128 iterate / f64 residual",
@@ -532,8 +597,8 @@ def main_c5(a):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     damp = 1e-3 * out["gn_hessvec"]["curvature_dm_H_dm"] / float((dm.double() ** 2).sum())
-    xs, norms, codec = api.fwi_gn_cg(ops, src8, d["rec_idx"], (-full).float(), damping=damp, cg_iters=steps, tol=1e-6,
-                                     precond="mg", maxit=a.maxit, restart=20)
+    xs, norms, _, codec = api.fwi_gn_cg(ops, src8, d["rec_idx"], (-full).float(), damping=damp, cg_iters=steps,
+                                        tol=1e-6, tol_sens=1e-4, precond="mg", maxit=a.maxit, restart=20)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out["gn_cg"] = {"seconds": dt, "sources": len(src8), "steps": steps, "code": codec, "damping": damp,
@@ -565,8 +630,9 @@ def main_c5(a):
             o.close()
         return ph
     out["frequency_continuation"] = {
-        "seconds": dt, "sources": len(src8), "windows": [list(w) for w, _, _ in hist],
-        "misfit_before_each_step": [p for _, p, _ in hist],
+        "seconds": dt, "sources": len(src8), "windows": [list(st["window"]) for st in hist],
+        "misfit_before_each_step": [st["misfit"] for st in hist],
+        "solver_iterations_per_step": [int(st["iters"].sum()) for st in hist],
         "model_error_over_initial": float((m - kt).double().norm()) / err0,
         "misfit_all_frequencies_initial": misfit_all(k0), "misfit_all_frequencies_final": misfit_all(m)}
     print(f"c5 frequency continuation done in {dt:.1f} s", file=sys.stderr, flush=True)

@@ -122,6 +122,16 @@ int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rh
  * nrhs = 0 is a no-op (f and e may then be NULL).
  */
 int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
+/*
+ * helm_resample -- bilinear resampling of a nodal field in [nz][nx] onto
+ * out [mz][mx] covering the same extent (output node (I, K) sits at input
+ * coordinates I (nz-1)/(mz-1), K (nx-1)/(mx-1); FP64 weights, float I/O, both
+ * device).  The inversion driver uses it to put the model and the absorbing
+ * layer on the grid with 10 points per wavelength at a window's highest
+ * frequency, where the network is retrained (Sec. 5, retraining details).
+ * in and out must not overlap.
+ */
+int helm_resample(const float* in, int nz, int nx, float* out, int mz, int mx, void* stream);
 /* Roots of the coarsest-level polynomial, in application order (host, c128 [*n]). */
 int helm_coarse_roots(helm_op_t op, double* roots, int* n);
 
@@ -217,8 +227,9 @@ int cnn_precond_train(cnn_net_t net, helm_op_t op, const cnn_train_opts* opt, ui
  * fwi_misfit_grad -- Phi = 1/2 sum_{f,s} || R u_fs - d_fs ||^2 with
  * u_fs = H_f^{-1} g_s, and dPhi/dm for the squared slowness m of the media.
  *   ops[nfreq]: one operator per frequency, all on the same grid and built
- *     from the same m (the gradient is taken with respect to that m; each
- *     operator's own omega and gamma enter it);
+ *     from the same m and gamma (checked on the device: HELM_EINVAL
+ *     otherwise; the gradient is taken with respect to that m, each
+ *     operator's own omega entering it);
  *   src_idx[nsrc], rec_idx[nrec] (host): flat node indices row * nx + col; the
  *     source of s is the grid delta g_s = e_src / (hx hz); receivers sample the
  *     wavefield at their nodes and must be distinct;
@@ -232,9 +243,12 @@ int cnn_precond_train(cnn_net_t net, helm_op_t op, const cnn_train_opts* opt, ui
  *   iters (host, may be NULL): [2][nfreq][nsrc] iterations of the forward
  *     then the adjoint solves.
  * All nfreq * nsrc forward solves go into one helm_solve batch, then all
- * adjoint solves.  Workspace (two c128 and one c64 field per (f, s)) is
- * allocated and freed inside the call.  Returns HELM_OK, HELM_NOT_CONVERGED if
- * any solve missed tol (outputs are still written), or a hard error.
+ * adjoint solves.  Workspace (two c128 and one c64 field per (f, s)) comes
+ * from a device pool that the FWI entry points share and keep between calls
+ * (fwi_release_workspace frees it); FWI calls are serialised.  Returns
+ * HELM_OK, HELM_NOT_CONVERGED if any solve missed tol (outputs are still
+ * written), HELM_ENAN if any solve produced a non-finite residual, or another
+ * hard error.
  */
 int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
                     const void* dobs, double tol, const helm_solve_opts* opt, double* misfit, float* grad,
@@ -273,13 +287,11 @@ int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const int* src_idx,
  *                      dd c64 [nfreq][nsrc][nrec] (device) -> out float [nz][nx] (device);
  *   fwi_gn_hessvec:    out = Re(J^H J dm), the Gauss-Newton Hessian of the misfit
  *                      applied to dm (what CG on the Gauss-Newton system needs).
- * Sources, receivers, tol and opt as for fwi_misfit_grad.  iters (host, may be
- * NULL) receives [nfreq][nsrc] per solve batch: forward then Born (fwi_born),
- * forward then adjoint (fwi_born_adjoint), forward, Born, adjoint
- * (fwi_gn_hessvec).  Each batch is one helm_solve call over all (f, s).
- * Workspace is allocated and freed inside the call.  Returns HELM_OK,
- * HELM_NOT_CONVERGED if any solve missed tol (outputs still written), or a hard
- * error.
+ * Sources, receivers, tol and opt as for fwi_misfit_grad (every solve at tol).
+ * iters (host, may be NULL) receives [nfreq][nsrc] per solve batch: forward
+ * then Born (fwi_born), forward then adjoint (fwi_born_adjoint), forward, Born,
+ * adjoint (fwi_gn_hessvec).  Each batch is one helm_solve call over all (f, s).
+ * Workspace from the shared FWI pool.  Returns as fwi_misfit_grad.
  */
 int fwi_born(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
              const float* dm, double tol, const helm_solve_opts* opt, void* jdm, int* iters, void* stream);
@@ -288,41 +300,78 @@ int fwi_born_adjoint(const helm_op_t* ops, int nfreq, const int* src_idx, int ns
 int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
                    const float* dm, double tol, const helm_solve_opts* opt, float* out, int* iters, void* stream);
 
-/*
- * fwi_gn_cg -- cg_iters conjugate-gradient steps from x = 0 on the damped
- * Gauss-Newton system (Re(J^H J) + damping I) x = b, the inner solve of a
- * Gauss-Newton step (Sec. 3.3, eq. (3.9)-(3.11)), with the products of
- * fwi_gn_hessvec: the point-source fields are computed once and reused, and
- * each step costs one Born and one adjoint solve batch.
- *   b, x: float [nz][nx] (device); the vector work is FP64 and dot products
- *     are folded in a fixed order (same bits on every run);
- *   resnorms (host, may be NULL): [cg_iters + 1] norms ||b - A x_k||;
- *   damping >= 0; sources, receivers, tol and opt as for fwi_born.
- * Stops early, with the remaining norms 0, when the residual is exactly 0.
- * Returns as fwi_born, or HELM_ENAN if p.Ap <= 0 (a direction without
- * curvature, possible only with damping 0).
- */
-int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
-              const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt, float* x,
-              double* resnorms, void* stream);
+/* Regularisers of the inversion's objective Phi(m) + alpha R(m) (Sec. 5):
+ * with d = m - m_ref, grad_h the forward differences between neighbouring
+ * nodes and Lap_h = -grad_h^T grad_h (each node sums (d_nb - d) / h^2 over the
+ * neighbours that exist),
+ *   FWI_REG_HIGH  R = ||Lap_h d||^2   (eq. (5.1), "spline smoothing"),
+ *   FWI_REG_DIFF  R = ||grad_h d||^2  (eq. (5.2), diffusion);
+ * sums over nodes and edges.  Gradients 2 Lap_h^2 d and -2 Lap_h d; Hessians
+ * 2 Lap_h^2 and -2 Lap_h (the alpha nabla^2 R term of eq. (3.11)). */
+#define FWI_REG_NONE 0
+#define FWI_REG_HIGH 1
+#define FWI_REG_DIFF 2
+
+/* Options of the Gauss-Newton entry points. */
+typedef struct {
+    double damping;       /* >= 0: damping * I is added to the Gauss-Newton matrix    */
+    int cg_iters;         /* conjugate-gradient steps (>= 0)                          */
+    double tol_sens;      /* tolerance of the Born and adjoint solves inside CG
+                             (Sec. 5.4 uses 1e-4); <= 0: the forward tol               */
+    int reg;              /* FWI_REG_NONE / FWI_REG_HIGH / FWI_REG_DIFF               */
+    double alpha;         /* weight of R (>= 0)                                       */
+    const float* m_ref;   /* reference model, float [nz][nx] (device); needed when reg != NONE */
+} fwi_gn_opts;
 
 /*
- * fwi_gn_step -- one Gauss-Newton step of the inversion (Sec. 3.3): the misfit
- * and gradient at m (as fwi_misfit_grad), dm from cg_iters conjugate-gradient
- * steps on (Re(J^H J) + damping I) dm = -grad (as fwi_gn_cg), and
- * m_new = m + mu dm.  One step of a window of Alg. 1 (frequency continuation).
- *   m: float [nz][nx] (device), the model the operators were set up with (the
- *     caller keeps them consistent); m_new (device) may alias m;
- *   dobs: c64 [nfreq][nsrc][nrec] (device); misfit (host): Phi(m);
- *   grad (device, float [nz][nx]): dPhi/dm at m; resnorms (host, may be NULL):
- *     [cg_iters + 1] CG residual norms.
+ * fwi_gn_cg -- g->cg_iters conjugate-gradient steps from x = 0 on the
+ * Gauss-Newton system (Re(J^H J) + alpha nabla^2 R + damping I) x = b, the
+ * inner solve of a Gauss-Newton step (Sec. 3.3, eq. (3.9)-(3.11)), with the
+ * products of fwi_gn_hessvec: the point-source fields are computed once (at
+ * tol) and reused, and each step costs one Born and one adjoint solve batch
+ * (at g->tol_sens).
+ *   b, x: float [nz][nx] (device); the vector work (and the regulariser's
+ *     Hessian) is FP64 and dot products are folded in a fixed order (same bits
+ *     on every run);
+ *   resnorms (host, may be NULL): [cg_iters + 1] norms ||b - A x_k||;
+ *   iters (host, may be NULL): [cg_iters][2][nfreq][nsrc], the Born then the
+ *     adjoint batch of each step (0 after an early stop);
+ *   sources, receivers, tol and opt as for fwi_born.
+ * Stops early, with the remaining norms 0, when the residual is exactly 0.
+ * Returns as fwi_born, or HELM_ENAN if p.Ap <= 0 (a direction without
+ * curvature, possible only without damping and regularisation).
+ */
+int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
+              const float* b, const fwi_gn_opts* g, double tol, const helm_solve_opts* opt, float* x,
+              double* resnorms, int* iters, void* stream);
+
+/*
+ * fwi_gn_step -- one Gauss-Newton step of the inversion (Sec. 3.3) on the
+ * objective Phi(m) + alpha R(m): the data misfit and gradient at m (as
+ * fwi_misfit_grad, at tol), plus alpha dR/dm; dm from g->cg_iters CG steps on
+ * (Re(J^H J) + alpha nabla^2 R + damping I) dm = -grad (as fwi_gn_cg, the
+ * sensitivities at g->tol_sens); m_new = m + mu dm.  One step of a window of
+ * Alg. 1 (frequency continuation).
+ *   m: float [nz][nx] (device), the model the operators were set up with
+ *     (checked: HELM_EINVAL otherwise); m_new (device) may alias m;
+ *   dobs: c64 [nfreq][nsrc][nrec] (device);
+ *   misfit (host): the data misfit Phi(m); reg_value (host, may be NULL): R(m);
+ *   grad (device, float [nz][nx]): dPhi/dm + alpha dR/dm at m;
+ *   resnorms (host, may be NULL): [cg_iters + 1] CG residual norms;
+ *   iters (host, may be NULL): [2 + 2 cg_iters][nfreq][nsrc]: the forward and
+ *     adjoint batches of the gradient, then the Born and adjoint batches of
+ *     each CG step.
  * The CG reuses the gradient's point-source fields: a step costs 2 + 2 cg_iters
- * solve batches.  Returns as fwi_born; EINVAL for a non-finite mu.
+ * solve batches.  Returns as fwi_gn_cg; EINVAL for a non-finite mu.
  */
 int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
-                const void* dobs, const float* m, double damping, int cg_iters, double mu, double tol,
-                const helm_solve_opts* opt, float* m_new, double* misfit, float* grad, double* resnorms,
-                void* stream);
+                const void* dobs, const float* m, const fwi_gn_opts* g, double mu, double tol,
+                const helm_solve_opts* opt, float* m_new, double* misfit, double* reg_value, float* grad,
+                double* resnorms, int* iters, void* stream);
+
+/* Frees the device workspace pool of the FWI entry points (the next call
+ * allocates it again).  Synchronises the device. */
+int fwi_release_workspace(void);
 
 /*
  * helm_autotune -- kernel selection for the network's convolutions.  With

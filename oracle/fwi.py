@@ -288,3 +288,19 @@ def frequency_continuation(kappa2, gamma, omegas, hx, src_idx, rec_idx, dobs, cy
                                           cg_iters, mu, hz, reg, alpha, m_ref)
                 history.append(phi)
     return m, np.array(history)
+
+
+def resample_bilinear(f, mz, mx):
+    """Bilinear interpolation of a nodal field [nz][nx] onto an mz x mx grid of
+    the same extent (node I at coordinate I (nz-1)/(mz-1) of the input grid),
+    by scipy's regular-grid linear interpolator: the grid the network is
+    retrained on after a window of Alg. 1 (Sec. 5, retraining details)."""
+    from scipy.interpolate import RegularGridInterpolator
+    f = np.asarray(f, np.float64)
+    nz, nx = f.shape
+    it = RegularGridInterpolator((np.arange(nz, dtype=np.float64), np.arange(nx, dtype=np.float64)), f,
+                                 method="linear")
+    z = np.arange(mz) * (nz - 1) / max(mz - 1, 1)
+    x = np.arange(mx) * (nx - 1) / max(mx - 1, 1)
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    return it(np.stack([Z.ravel(), X.ravel()], axis=1)).reshape(mz, mx)

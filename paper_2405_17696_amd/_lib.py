@@ -48,6 +48,13 @@ class TrainOpts(C.Structure):
                 ("steps_done", C.POINTER(C.c_int)), ("dataset_size", C.POINTER(C.c_int))]
 
 
+class GnOpts(C.Structure):
+    _fields_ = [("damping", C.c_double), ("cg_iters", C.c_int), ("tol_sens", C.c_double), ("reg", C.c_int),
+                ("alpha", C.c_double), ("m_ref", C.c_void_p)]
+
+
+FWI_REG = {"none": 0, "high": 1, "diff": 2}
+
 _lib = None
 
 # name -> (restype, argtypes); every exported symbol of include/*.h is listed here
@@ -62,6 +69,7 @@ SIGNATURES = {
                              C.c_int, C.c_double, C.POINTER(SolveOpts), C.POINTER(C.c_int),
                              C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
     "helm_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "helm_resample": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
     "helm_coarse_roots": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "cnn_create": (C.c_int, [C.POINTER(CnnArch), C.c_uint64, C.POINTER(C.c_void_p)]),
     "cnn_destroy": (None, [C.c_void_p]),
@@ -100,12 +108,13 @@ SIGNATURES = {
                                  C.c_int, C.c_void_p, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
                                  C.POINTER(C.c_int), C.c_void_p]),
     "fwi_gn_cg": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.c_int,
-                            C.c_void_p, C.c_double, C.c_int, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
-                            C.POINTER(C.c_double), C.c_void_p]),
+                            C.c_void_p, C.POINTER(GnOpts), C.c_double, C.POINTER(SolveOpts), C.c_void_p,
+                            C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
     "fwi_gn_step": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int),
-                              C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
-                              C.POINTER(SolveOpts), C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
-                              C.POINTER(C.c_double), C.c_void_p]),
+                              C.c_int, C.c_void_p, C.c_void_p, C.POINTER(GnOpts), C.c_double, C.c_double,
+                              C.POINTER(SolveOpts), C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
+    "fwi_release_workspace": (C.c_int, []),
     "cnn_precond_train": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(TrainOpts), C.c_uint64,
                                     C.POINTER(C.c_float), C.c_void_p]),
     "cnn_layer_forward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 5 + [C.c_int, C.c_void_p]),

@@ -86,6 +86,16 @@ def helm_vcycle(op: HelmOp, f: torch.Tensor, e: torch.Tensor | None = None) -> t
     return e
 
 
+def helm_resample(f: torch.Tensor, mz: int, mx: int) -> torch.Tensor:
+    """Bilinear resampling of a float32 [nz][nx] device field onto [mz][mx] (same extent)."""
+    if f.dtype != torch.float32 or f.dim() != 2:
+        raise TypeError("helm_resample takes a float32 [nz][nx] tensor")
+    f = f.contiguous()
+    out = torch.empty((mz, mx), dtype=torch.float32, device=f.device)
+    L.check(L.load().helm_resample(_ptr(f), f.shape[0], f.shape[1], _ptr(out), int(mz), int(mx), _stream()))
+    return out
+
+
 def helm_coarse_roots(op: HelmOp):
     import numpy as np
     lib = L.load()
@@ -460,12 +470,26 @@ def fwi_gn_hessvec(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, p
                     use_graph, reorth, net)
 
 
+def _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref):
+    if reg not in L.FWI_REG:
+        raise ValueError(f"reg must be one of {sorted(L.FWI_REG)}")
+    if reg != "none":
+        if m_ref is None:
+            raise ValueError("the regulariser needs m_ref")
+        if m_ref.dtype != torch.float32 or not m_ref.is_contiguous():
+            raise ValueError("m_ref must be a contiguous float32 tensor")
+    return L.GnOpts(float(damping), int(cg_iters), float(tol_sens), L.FWI_REG[reg], float(alpha),
+                    C.c_void_p(m_ref.data_ptr() if m_ref is not None else None))
+
+
 def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_iters: int = 10, tol: float = 1e-6,
+              tol_sens: float = 0.0, reg: str = "none", alpha: float = 0.0, m_ref: torch.Tensor | None = None,
               precond: str = "mg", restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64",
               use_graph: bool = False, reorth: bool = False, net=None):
-    """cg_iters CG steps on (Re(J^H J) + damping I) x = b from x = 0; b float32
-    [nz][nx] on the GPU.  Returns (x float32 [nz][nx], residual norms
-    [cg_iters + 1], code)."""
+    """cg_iters CG steps on (Re(J^H J) + alpha nabla^2 R + damping I) x = b from
+    x = 0; b float32 [nz][nx] on the GPU; the point-source fields at tol, the
+    Born and adjoint solves at tol_sens (<= 0: tol).  Returns (x float32
+    [nz][nx], residual norms [cg_iters + 1], iters [cg_iters][2][nfreq][nsrc], code)."""
     import numpy as np
     lib = L.load()
     if isinstance(ops, HelmOp):
@@ -478,23 +502,29 @@ def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_i
     b = b.contiguous()
     x = torch.empty((ops[0].nz, ops[0].nx), dtype=torch.float32, device=b.device)
     handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    g = _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref)
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
                     int(reorth), C.c_void_p(net.handle.value if net is not None else None))
     norms = (C.c_double * (cg_iters + 1))()
-    code = lib.fwi_gn_cg(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(b), float(damping),
-                         int(cg_iters), float(tol), C.byref(o), _ptr(x), norms, _stream())
+    its = (C.c_int * max(1, 2 * cg_iters * nf * ns))()
+    code = lib.fwi_gn_cg(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(b), C.byref(g),
+                         float(tol), C.byref(o), _ptr(x), norms, its, _stream())
     L.check(code, soft_ok=True)
-    return x, np.array(norms[:], dtype=np.float64), code
+    it = np.array(its[:2 * cg_iters * nf * ns], dtype=np.int64).reshape(cg_iters, 2, nf, ns)
+    return x, np.array(norms[:], dtype=np.float64), it, code
 
 
 def fwi_gn_step(ops, src_idx, rec_idx, dobs: torch.Tensor, m: torch.Tensor, damping: float, cg_iters: int,
-                mu: float = 1.0, tol: float = 1e-6, precond: str = "mg", restart: int = 0, maxit: int = 300,
+                mu: float = 1.0, tol: float = 1e-6, tol_sens: float = 0.0, reg: str = "none", alpha: float = 0.0,
+                m_ref: torch.Tensor | None = None, precond: str = "mg", restart: int = 0, maxit: int = 300,
                 krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None,
                 m_new: torch.Tensor | None = None):
-    """One Gauss-Newton step m + mu dm, dm from CG on (Re(J^H J) + damping I) dm =
-    -grad; ops must be set up with m.  Returns (m_new, misfit at m, grad,
-    CG residual norms, code)."""
+    """One Gauss-Newton step m + mu dm on Phi + alpha R, dm from CG on
+    (Re(J^H J) + alpha nabla^2 R + damping I) dm = -grad; ops must be set up
+    with m.  Returns a dict: m_new, misfit (data misfit at m), reg (R(m)),
+    grad (dPhi/dm + alpha dR/dm), norms (CG residual norms), iters
+    [2 + 2 cg_iters][nfreq][nsrc], code."""
     import numpy as np
     lib = L.load()
     if isinstance(ops, HelmOp):
@@ -510,16 +540,27 @@ def fwi_gn_step(ops, src_idx, rec_idx, dobs: torch.Tensor, m: torch.Tensor, damp
     m_new = torch.empty_like(m) if m_new is None else m_new
     grad = torch.empty_like(m)
     handles = (C.c_void_p * nf)(*[o.handle for o in ops])
+    g = _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref)
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
                     int(reorth), C.c_void_p(net.handle.value if net is not None else None))
     phi = C.c_double()
+    rv = C.c_double()
     norms = (C.c_double * (cg_iters + 1))()
+    nb = 2 + 2 * cg_iters
+    its = (C.c_int * (nb * nf * ns))()
     code = lib.fwi_gn_step(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(dobs), _ptr(m),
-                           float(damping), int(cg_iters), float(mu), float(tol), C.byref(o), _ptr(m_new),
-                           C.byref(phi), _ptr(grad), norms, _stream())
+                           C.byref(g), float(mu), float(tol), C.byref(o), _ptr(m_new), C.byref(phi), C.byref(rv),
+                           _ptr(grad), norms, its, _stream())
     L.check(code, soft_ok=True)
-    return m_new, phi.value, grad, np.array(norms[:], dtype=np.float64), code
+    return {"m_new": m_new, "misfit": phi.value, "reg": rv.value, "grad": grad,
+            "norms": np.array(norms[:], dtype=np.float64),
+            "iters": np.array(its[:], dtype=np.int64).reshape(nb, nf, ns), "code": code}
+
+
+def fwi_release_workspace():
+    """Free the FWI entry points' device workspace pool."""
+    L.check(L.load().fwi_release_workspace())
 
 
 class FwiMisfit(torch.autograd.Function):

@@ -8,9 +8,10 @@ namespace helm {
 int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s);
 // e = SolverNet(scale_r * r) / scale_r for nrhs vectors of op's grid (c64, or c128
 // when wide != 0), skipping RHS whose state is inactive.  scale_r comes from
-// fscale[(rhs0 + r) * fstride] (may be null: 1).
+// fscale[(rhs0 + r) * fstride] (may be null: 1).  fallback: e = 0 for a RHS
+// whose network output is not finite.
 int cnn_apply_masked(cnn_net* net, const helm_op* op, const void* r, const double* fscale, int fstride, void* e,
-                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s);
+                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s, bool fallback = false);
 // Drop any encoder context cached on op.
 void cnn_release_cache(helm_op* op);
 

@@ -227,16 +227,43 @@ __global__ void k_pack(const cx<T>* __restrict__ v, long N, const double* __rest
     }
 }
 
-// e_b = mul_b * (out[b][p][0] + i out[b][p][1])
+// e_b = mul_b * (out[b][p][0] + i out[b][p][1]); e_b = 0 for a sample flagged
+// in bad (non-finite network output), when bad is given.
 template <typename T>
 __global__ void k_unpack(const float* __restrict__ out, long N, const double* __restrict__ mul, int mstride,
-                         cx<T>* __restrict__ e) {
+                         const int* __restrict__ bad, cx<T>* __restrict__ e) {
     const int b = blockIdx.y;
     long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     double m = mul[(long)b * mstride];
+    if (bad && bad[b]) m = 0.0;
     long o = ((long)b * N + p) * 2;
-    e[(long)b * N + p] = mk(T(m * out[o]), T(m * out[o + 1]));
+    const float re = out[o], im = out[o + 1];
+    e[(long)b * N + p] = m == 0.0 ? mk(T(0), T(0)) : mk(T(m * re), T(m * im));
+}
+
+__global__ void k_fill_int(int* __restrict__ a, int n, int v) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
+// bad[b] = 1 when the network output of sample b holds a non-finite value
+// (bad zeroed beforehand; one atomic per wave that sees one).
+__global__ __launch_bounds__(256) void k_finite_flags(const float* __restrict__ out, long N,
+                                                      const RhsState* __restrict__ st, int rhs0,
+                                                      int* __restrict__ bad) {
+    const int b = blockIdx.y;
+    if (st) {
+        const RhsState& S = st[rhs0 + b];
+        if (!S.active || S.cycdone) return;
+    }
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool nf = false;
+    if (p < N) {
+        const float2 v = reinterpret_cast<const float2*>(out)[(long)b * N + p];
+        nf = !(__builtin_isfinite(v.x) && __builtin_isfinite(v.y));
+    }
+    if (__any(nf) && (threadIdx.x & 63) == 0) atomicOr(&bad[b], 1);
 }
 
 // Per-sample scale factors inside FGMRES: the raw basis vector V[j] enters with
@@ -1048,17 +1075,23 @@ void cnn_release_cache(helm_op* op) {
     op->enc.ctx = nullptr;
 }
 
-// Per-batch-size scale buffers (s_in, s_out per RHS), allocated once.
-static int scale_bufs(int nrhs, double** sin, double** sout) {
-    static std::map<int, std::pair<double*, double*>> sbuf;
+// Per-batch-size scale buffers (s_in, s_out per RHS) and the per-RHS flags of
+// non-finite network outputs, allocated once.
+struct ScaleBufs {
+    double* sin = nullptr;
+    double* sout = nullptr;
+    int* bad = nullptr;
+};
+static int scale_bufs(int nrhs, ScaleBufs* out) {
+    static std::map<int, ScaleBufs> sbuf;
     auto& sb = sbuf[nrhs];
-    if (!sb.first) {
-        if (hipMalloc(&sb.first, sizeof(double) * nrhs) != hipSuccess ||
-            hipMalloc(&sb.second, sizeof(double) * nrhs) != hipSuccess)
+    if (!sb.sin) {
+        if (hipMalloc(&sb.sin, sizeof(double) * nrhs) != hipSuccess ||
+            hipMalloc(&sb.sout, sizeof(double) * nrhs) != hipSuccess ||
+            hipMalloc(&sb.bad, sizeof(int) * nrhs) != hipSuccess)
             return fail(HELM_ENOMEM, "cnn: scale buffers");
     }
-    *sin = sb.first;
-    *sout = sb.second;
+    *out = sb;
     return HELM_OK;
 }
 
@@ -1072,48 +1105,58 @@ int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s) {
     Arena* A;
     if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
     if ((rc = ensure_encoded(net, op, A, s))) return rc;
-    double *a, *b;
-    return scale_bufs(nrhs, &a, &b);
+    ScaleBufs sb;
+    return scale_bufs(nrhs, &sb);
 }
 
 // e = M_net(r) for nrhs vectors.  Scales: s_in = sqrt(N) fscale (FGMRES basis
 // vectors have unit norm after scaling) or sqrt(N)/||r|| when fscale is null.
+// With fallback, a right-hand side whose network output holds a non-finite
+// value gets e = 0 instead (inside M_VU that leaves the V-cycle alone for it).
 template <typename T>
 static int apply_impl(cnn_net* net, const helm_op* op, const cx<T>* r, const double* fscale, int fstride, cx<T>* e,
-                      int nrhs, const RhsState* st, int rhs0, hipStream_t s) {
+                      int nrhs, const RhsState* st, int rhs0, hipStream_t s, bool fallback = false) {
     int rc;
     if ((rc = check_grid(op))) return rc;
     Arena* A;
     if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
     if ((rc = ensure_encoded(net, op, A, s))) return rc;
-    std::pair<double*, double*> sb;
-    if ((rc = scale_bufs(nrhs, &sb.first, &sb.second))) return rc;
+    ScaleBufs sb;
+    if ((rc = scale_bufs(nrhs, &sb))) return rc;
     const long N = op->n();
     const double sqrtN = std::sqrt((double)N), h2 = op->hx * op->hz;
     if (fscale) {
         hipLaunchKernelGGL(k_scales_from_vscale, dim3((nrhs + 63) / 64), dim3(64), 0, s, fscale + (long)rhs0 * fstride,
-                           fstride, nrhs, sqrtN, h2, sb.first, sb.second);
+                           fstride, nrhs, sqrtN, h2, sb.sin, sb.sout);
     } else {
-        hipLaunchKernelGGL(k_sample_scale<T>, dim3(nrhs), dim3(256), 0, s, r, N, sqrtN, h2, sb.first, sb.second);
+        hipLaunchKernelGGL(k_sample_scale<T>, dim3(nrhs), dim3(256), 0, s, r, N, sqrtN, h2, sb.sin, sb.sout);
     }
     HELM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, s, r, N, sb.first, 1,
+    hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, s, r, N, sb.sin, 1,
                        A->sol.t[A->sol.input].d, (float*)nullptr);
     HELM_CHECK_LAUNCH();
     if ((rc = run_forward(net, *A, A->sol, st, rhs0, s))) return rc;
-    hipLaunchKernelGGL(k_unpack<T>, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, s, A->sol.outf, N,
-                       sb.second, 1, e);
+    const dim3 grid((unsigned)((N + 255) / 256), nrhs);
+    if (fallback) {
+        // a fill kernel, not a memset, so that the step can be graph-captured
+        hipLaunchKernelGGL(k_fill_int, dim3((nrhs + 255) / 256), dim3(256), 0, s, sb.bad, nrhs, 0);
+        HELM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_finite_flags, grid, dim3(256), 0, s, A->sol.outf, N, st, rhs0, sb.bad);
+        HELM_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_unpack<T>, grid, dim3(256), 0, s, A->sol.outf, N, sb.sout, 1,
+                       fallback ? (const int*)sb.bad : nullptr, e);
     HELM_CHECK_LAUNCH();
     return HELM_OK;
 }
 
 int cnn_apply_masked(cnn_net* net, const helm_op* op, const void* r, const double* fscale, int fstride, void* e,
-                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s) {
+                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s, bool fallback) {
     std::lock_guard<std::recursive_mutex> lk(g_cnn_mutex);
     // fscale arrives offset to the current Arnoldi column; apply_impl adds rhs0*stride
     if (wide)
-        return apply_impl<double>(net, op, (const c128*)r, fscale, fstride, (c128*)e, nrhs, st, rhs0, s);
-    return apply_impl<float>(net, op, (const c64*)r, fscale, fstride, (c64*)e, nrhs, st, rhs0, s);
+        return apply_impl<double>(net, op, (const c128*)r, fscale, fstride, (c128*)e, nrhs, st, rhs0, s, fallback);
+    return apply_impl<float>(net, op, (const c64*)r, fscale, fstride, (c64*)e, nrhs, st, rhs0, s, fallback);
 }
 
 // ------------------------------------------------------------------ training

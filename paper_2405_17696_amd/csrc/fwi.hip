@@ -13,6 +13,10 @@
 // The last line follows from dH_f/dm_k = -w_f^2 (1 - i gamma_k) e_k e_k^T
 // (eq. 3.1); the Jacobian printed with eq. (3.10) carries the opposite sign.
 //
+// Gauss-Newton (Sec. 3.3, eq. 3.9-3.11): products with J and J^H, conjugate
+// gradients on (Re(J^H J) + alpha nabla^2 R + damping I) dm = -grad, and one
+// step m + mu dm, with the regularisers R_high and R_diff of eq. 5.1 and 5.2.
+//
 // Simultaneous sources (Sec. 3.2, eq. 3.6-3.8): with an ns x p matrix X of
 // Rademacher columns (drawn by the caller), the frequency's source sum is
 // replaced by the trace estimate (1/p) sum_i || R H_f^{-1} G x_i - D_f x_i ||^2:
@@ -21,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -197,23 +202,94 @@ __global__ void k_to_float(const double* __restrict__ a, long n, float* __restri
     if (t < n) b[t] = (float)a[t];
 }
 
-struct Owned {
-    std::vector<void*> p;
-    ~Owned() {
-        for (void* q : p) (void)hipFree(q);
+// ------------------------------------------------------------------ regularisers (eq. 5.1, 5.2)
+// R_high = ||Lap_h (m - m_ref)||^2 and R_diff = ||grad_h (m - m_ref)||^2 with
+// grad_h the forward differences between neighbouring nodes and
+// Lap_h = -grad_h^T grad_h (each node sums (d_nb - d) / h^2 over the
+// neighbours that exist).  Gradients 2 Lap_h^2 d and -2 Lap_h d, Hessians
+// 2 Lap_h^2 and -2 Lap_h; all FP64.
+
+// d = m - m_ref (FP64)
+__global__ void k_model_diff(const float* __restrict__ m, const float* __restrict__ mref, long n,
+                             double* __restrict__ d) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) d[t] = (double)m[t] - (double)mref[t];
+}
+
+// out = Lap_h d (nodal-gradient closure)
+__global__ void k_reg_lap(const double* __restrict__ d, int nz, int nx, double ax, double az,
+                          double* __restrict__ out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nz * nx) return;
+    const int i = (int)(t / nx), k = (int)(t - (long)i * nx);
+    const double c = d[t];
+    double acc = 0;
+    if (k > 0) acc += ax * (d[t - 1] - c);
+    if (k + 1 < nx) acc += ax * (d[t + 1] - c);
+    if (i > 0) acc += az * (d[t - nx] - c);
+    if (i + 1 < nz) acc += az * (d[t + nx] - c);
+    out[t] = acc;
+}
+
+// y += a x
+__global__ void k_axpy_d(double* __restrict__ y, const double* __restrict__ x, double a, long n) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+
+// Number of entries where a and b differ (bit patterns), one atomic per wave that sees one.
+__global__ void k_count_diff(const float* __restrict__ a, const float* __restrict__ b, long n, int* __restrict__ cnt) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool d = t < n && __float_as_uint(a[t]) != __float_as_uint(b[t]);
+    if (__any(d) && (threadIdx.x & 63) == 0) atomicAdd(cnt, 1);
+}
+
+// ------------------------------------------------------------------ workspace
+// Device workspace of the FWI entry points, grown on demand and kept for the
+// next call: a call on the 512 x 512, 4-frequency, 128-source setting needs
+// several GB, and the Gauss-Newton driver calls these entry points once per
+// step.  A call takes the pool's slots in order; calls are serialised by
+// g_fwi_mutex, and every entry point synchronises its stream before it
+// returns, so a slot is never in use when the next call takes it.
+struct Pool {
+    std::vector<std::pair<void*, size_t>> slot;
+    size_t next = 0;
+    void release() {
+        for (auto& sl : slot)
+            if (sl.first) (void)hipFree(sl.first);
+        slot.clear();
+        next = 0;
     }
+};
+static Pool g_pool;
+static std::recursive_mutex g_fwi_mutex;
+
+struct Owned {
+    Owned() { g_pool.next = 0; }
     template <typename T>
     T* get(size_t n) {
-        void* q = nullptr;
-        if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
-        p.push_back(q);
-        return (T*)q;
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (g_pool.next == g_pool.slot.size()) g_pool.slot.push_back({nullptr, 0});
+        auto& sl = g_pool.slot[g_pool.next++];
+        if (sl.second < bytes) {
+            if (sl.first) (void)hipFree(sl.first);
+            sl = {nullptr, 0};
+            if (hipMalloc(&sl.first, bytes) != hipSuccess) {
+                sl.first = nullptr;
+                return nullptr;
+            }
+            sl.second = bytes;
+        }
+        return (T*)sl.first;
     }
 };
 
-// Checks shared by both entry points.
+// Checks shared by the entry points: one grid, in-range sources, distinct
+// in-range receivers, and one medium (every operator's m and gamma equal to
+// ops[0]'s, and to m when it is given: the gradient and the model update refer
+// to that one model).
 static int check_args(const char* name, const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
-                      const int* rec_idx, int nrec) {
+                      const int* rec_idx, int nrec, hipStream_t s, Owned& own, const float* m = nullptr) {
     for (int f = 0; f < nfreq; ++f) {
         if (!ops[f]) return fail(HELM_EINVAL, "%s: ops[%d] is NULL", name, f);
         const helm_op* a = ops[f];
@@ -230,28 +306,71 @@ static int check_args(const char* name, const helm_op_t* ops, int nfreq, const i
         if (rs[i] < 0 || rs[i] >= N) return fail(HELM_EINVAL, "%s: receiver index out of range", name);
         if (i && rs[i] == rs[i - 1]) return fail(HELM_EINVAL, "%s: receiver nodes must be distinct", name);
     }
+    const int ncmp = 2 * (nfreq - 1) + (m ? 1 : 0);
+    if (ncmp == 0) return HELM_OK;
+    int* cnt = own.get<int>(ncmp);
+    if (!cnt) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    HELM_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * ncmp, s));
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    for (int f = 1; f < nfreq; ++f) {
+        hipLaunchKernelGGL(k_count_diff, dim3(nb), dim3(256), 0, s, ops[f]->lv[0].k2, ops[0]->lv[0].k2, N,
+                           cnt + 2 * (f - 1));
+        hipLaunchKernelGGL(k_count_diff, dim3(nb), dim3(256), 0, s, ops[f]->lv[0].g, ops[0]->lv[0].g, N,
+                           cnt + 2 * (f - 1) + 1);
+    }
+    if (m) hipLaunchKernelGGL(k_count_diff, dim3(nb), dim3(256), 0, s, m, ops[0]->lv[0].k2, N, cnt + ncmp - 1);
+    HELM_CHECK_LAUNCH();
+    std::vector<int> h(ncmp);
+    HELM_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int) * ncmp, hipMemcpyDeviceToHost, s));
+    HELM_HIP(hipStreamSynchronize(s));
+    for (int f = 1; f < nfreq; ++f)
+        if (h[2 * (f - 1)] || h[2 * (f - 1) + 1])
+            return fail(HELM_EINVAL, "%s: operator %d was set up with another model or attenuation than operator 0",
+                        name, f);
+    if (m && h[ncmp - 1]) return fail(HELM_EINVAL, "%s: m is not the model the operators were set up with", name);
     return HELM_OK;
+}
+
+// One batched solve inside an FWI entry point: the per-RHS HELM_ENAN that
+// helm_solve reports as a soft failure is a hard error here (a non-finite
+// field would enter the misfit, gradient or model update).
+static int fwi_solve(const char* name, const helm_op_t* ops, int nfreq, const std::vector<int>& rhs_op,
+                     const c64* rhs, c128* x, double tol, const helm_solve_opts& o, int* it, hipStream_t s) {
+    const int nfs = (int)rhs_op.size();
+    std::vector<int> st(nfs);
+    const int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, x, nfs, tol, &o, it, nullptr, st.data(), s);
+    if (rc < 0) return rc;
+    for (int i = 0; i < nfs; ++i)
+        if (st[i] == HELM_ENAN)
+            return fail(HELM_ENAN, "%s: solve %d (frequency %d) produced a non-finite residual", name, i,
+                        rhs_op[i]);
+    return rc;
 }
 
 // From nper prepared right-hand sides per frequency (rhs, zero outside the
 // sources) and their data dobs_d [nfreq][nper][nrec] (device): forward solves,
-// residuals and misfit, adjoint solves, gradient; misfit and gradient times scale.
-static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs, const c64* dobs_d,
-                            const int* rec_d, int nrec, double tol, helm_solve_opts o, double scale, double* misfit,
-                            float* grad, int* iters, hipStream_t s, Owned& own, c128* u_keep = nullptr) {
+// residuals and misfit, adjoint solves, gradient; misfit and gradient times
+// scale, plus extra (device FP64 [N], may be NULL) added to the gradient before
+// it is rounded to float.  u_keep / lam_buf: caller-owned field buffers
+// (nfreq * nper c128 fields each), else taken from the workspace.
+static int misfit_grad_core(const char* name, const helm_op_t* ops, int nfreq, int nper, c64* rhs,
+                            const c64* dobs_d, const int* rec_d, int nrec, double tol, helm_solve_opts o,
+                            double scale, double* misfit, float* grad, int* iters, hipStream_t s, Owned& own,
+                            c128* u_keep = nullptr, c128* lam_buf = nullptr, const double* extra = nullptr) {
     const long N = ops[0]->n();
     const int nfs = nfreq * nper;
-    c128* u = u_keep ? u_keep : own.get<c128>((size_t)nfs * N);   // u_keep: the caller keeps the fields
-    c128* lam = own.get<c128>((size_t)nfs * N);
+    c128* u = u_keep ? u_keep : own.get<c128>((size_t)nfs * N);
+    c128* lam = lam_buf ? lam_buf : own.get<c128>((size_t)nfs * N);
     double* gacc = own.get<double>(N);
     double* part = own.get<double>(nfs);
-    if (!u || !lam || !gacc || !part) return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
+    if (!u || !lam || !gacc || !part) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     std::vector<int> rhs_op(nfs);
     for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nper;
-    std::vector<int> st(nfs), it(nfs);
+    std::vector<int> it(nfs);
 
     // forward solves
-    int rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, u, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+    o.adjoint = 0;
+    int rc = fwi_solve(name, ops, nfreq, rhs_op, rhs, u, tol, o, it.data(), s);
     if (rc < 0) return rc;
     int worst = rc;
     if (iters) std::copy(it.begin(), it.end(), iters);
@@ -265,7 +384,7 @@ static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs,
 
     // adjoint solves: lambda = H^{-*} R^T res
     o.adjoint = 1;
-    rc = helm_solve(ops, nfreq, rhs_op.data(), rhs, lam, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+    rc = fwi_solve(name, ops, nfreq, rhs_op, rhs, lam, tol, o, it.data(), s);
     if (rc < 0) return rc;
     worst = std::max(worst, rc);
     if (iters) std::copy(it.begin(), it.end(), iters + nfs);
@@ -277,6 +396,10 @@ static int misfit_grad_core(const helm_op_t* ops, int nfreq, int nper, c64* rhs,
         hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, u + (size_t)f * nper * N,
                            lam + (size_t)f * nper * N, (const float*)ops[f]->lv[0].g, w2, nper, N, f == 0 ? 1 : 0,
                            gacc);
+        HELM_CHECK_LAUNCH();
+    }
+    if (extra) {
+        hipLaunchKernelGGL(k_axpy_d, dim3(nb), dim3(256), 0, s, gacc, extra, 1.0, N);
         HELM_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, gacc, N, grad);
@@ -298,40 +421,40 @@ struct BornWork {
     double* gacc = nullptr;
 };
 
-static int born_alloc(Owned& own, long N, int nfs, long nd, BornWork& W) {
+static int born_alloc(const char* name, Owned& own, long N, int nfs, long nd, BornWork& W) {
     W.rhs = own.get<c64>((size_t)nfs * N);
     W.u = own.get<c128>((size_t)nfs * N);
     W.w = own.get<c128>((size_t)nfs * N);
     W.jd = own.get<c64>((size_t)nd);
     W.gacc = own.get<double>(N);
-    if (!W.rhs || !W.u || !W.w || !W.jd || !W.gacc) return fail(HELM_ENOMEM, "fwi born: workspace allocation failed");
+    if (!W.rhs || !W.u || !W.w || !W.jd || !W.gacc) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     return HELM_OK;
 }
 
 // Linearised data and its adjoint (eq. 3.10, with the sign derived from
-// eq. 3.1): from the point-source fields u_fs (computed into W.u unless
-// have_u),
+// eq. 3.1): from the point-source fields u_fs (computed into W.u at tol_fwd
+// unless have_u),
 //   J dm      = R H_f^{-1} (w_f^2 (1 - i gamma) u_fs dm)          (when dm != NULL)
 //   Re(J^H d) = sum_fs w_f^2 Re(conj(H_f^{-*} R^T d_fs) (1 - i gamma) u_fs)
-// with d = dd, or d = J dm when dd is NULL (the Gauss-Newton product).  jdm
-// (device c64 [nfreq][nsrc][nrec], may be NULL) receives J dm, out (device
-// float [nz][nx], may be NULL) Re(J^H d); iters receives one [nfreq][nsrc]
-// block per solve batch in the order forward, Born, adjoint.
-static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d, int nrec,
-                     const float* dm, const c64* dd, c64* jdm, float* out, double tol, helm_solve_opts o, int* iters,
-                     hipStream_t s, const BornWork& W, bool have_u) {
+// with d = dd, or d = J dm when dd is NULL (the Gauss-Newton product); the
+// Born and adjoint solves run at tol_lin.  jdm (device c64
+// [nfreq][nsrc][nrec], may be NULL) receives J dm, out (device float [nz][nx],
+// may be NULL) Re(J^H d); iters receives one [nfreq][nsrc] block per solve
+// batch in the order forward, Born, adjoint.
+static int born_core(const char* name, const helm_op_t* ops, int nfreq, int nsrc, const int* src_d,
+                     const int* rec_d, int nrec, const float* dm, const c64* dd, c64* jdm, float* out, double tol_fwd,
+                     double tol_lin, helm_solve_opts o, int* iters, hipStream_t s, const BornWork& W, bool have_u) {
     const long N = ops[0]->n();
     const int nfs = nfreq * nsrc;
     const long nd = (long)nfs * nrec;
     c64* jd = jdm ? jdm : W.jd;
     std::vector<int> rhs_op(nfs);
     for (int i = 0; i < nfs; ++i) rhs_op[i] = i / nsrc;
-    std::vector<int> st(nfs), it(nfs);
+    std::vector<int> it(nfs);
     int worst = HELM_OK, stage = 0;
-    auto solve = [&](c128* x, int adjoint) {
+    auto solve = [&](c128* x, int adjoint, double tol) {
         o.adjoint = adjoint;
-        const int rc =
-            helm_solve(ops, nfreq, rhs_op.data(), W.rhs, x, nfs, tol, &o, it.data(), nullptr, st.data(), s);
+        const int rc = fwi_solve(name, ops, nfreq, rhs_op, W.rhs, x, tol, o, it.data(), s);
         if (rc >= 0) {
             worst = std::max(worst, rc);
             if (iters) std::copy(it.begin(), it.end(), iters + (size_t)stage * nfs);
@@ -350,7 +473,7 @@ static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d
         hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp,
                            W.rhs);
         HELM_CHECK_LAUNCH();
-        if ((rc = solve(W.u, 0)) < 0) return rc;
+        if ((rc = solve(W.u, 0, tol_fwd)) < 0) return rc;
     }
 
     // J dm
@@ -361,7 +484,7 @@ static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d
                                W.rhs + (size_t)f * nsrc * N);
             HELM_CHECK_LAUNCH();
         }
-        if ((rc = solve(W.w, 0)) < 0) return rc;
+        if ((rc = solve(W.w, 0, tol_lin)) < 0) return rc;
         hipLaunchKernelGGL(k_sample_rec, dim3(gd), dim3(256), 0, s, W.w, rec_d, nrec, N, nd, jd);
         HELM_CHECK_LAUNCH();
     }
@@ -371,7 +494,7 @@ static int born_core(const helm_op_t* ops, int nfreq, int nsrc, const int* src_d
         HELM_HIP(hipMemsetAsync(W.rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
         hipLaunchKernelGGL(k_scatter_rec, dim3(gd), dim3(256), 0, s, dd ? dd : jd, rec_d, nrec, N, nd, W.rhs);
         HELM_CHECK_LAUNCH();
-        if ((rc = solve(W.w, 1)) < 0) return rc;
+        if ((rc = solve(W.w, 1, tol_lin)) < 0) return rc;
         for (int f = 0; f < nfreq; ++f) {
             hipLaunchKernelGGL(k_fwi_grad_freq, dim3(nb), dim3(256), 0, s, W.u + (size_t)f * nsrc * N,
                                W.w + (size_t)f * nsrc * N, (const float*)ops[f]->lv[0].g,
@@ -393,6 +516,138 @@ static int solve_opts(const helm_solve_opts* opt, const char* name, helm_solve_o
     return HELM_OK;
 }
 
+// Deterministic FP64 dot product: fixed blocks, partials added on the host in order.
+static int dot_d(const double* a, const double* b, long n, double* part, double* result, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dot, dim3(CG_BLOCKS), dim3(256), 0, s, a, b, n, part);
+    HELM_CHECK_LAUNCH();
+    double hp[CG_BLOCKS];
+    HELM_HIP(hipMemcpyAsync(hp, part, sizeof(double) * CG_BLOCKS, hipMemcpyDeviceToHost, s));
+    HELM_HIP(hipStreamSynchronize(s));
+    double acc = 0;
+    for (int i = 0; i < CG_BLOCKS; ++i) acc += hp[i];
+    *result = acc;
+    return HELM_OK;
+}
+
+// Regulariser terms around d: out = coef * (Hessian of R) v for v (device FP64
+// [N]), added to out (FP64): R_high: 2 Lap^2 v, R_diff: -2 Lap v.  tmp, tmp2: [N].
+static int reg_hess_add(const helm_op* op, int kind, double coef, const double* v, double* out, double* tmp,
+                        double* tmp2, hipStream_t s) {
+    const long N = op->n();
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    const double ax = 1.0 / (op->hx * op->hx), az = 1.0 / (op->hz * op->hz);
+    hipLaunchKernelGGL(k_reg_lap, dim3(nb), dim3(256), 0, s, v, op->nz, op->nx, ax, az, tmp);
+    HELM_CHECK_LAUNCH();
+    if (kind == FWI_REG_HIGH) {
+        hipLaunchKernelGGL(k_reg_lap, dim3(nb), dim3(256), 0, s, tmp, op->nz, op->nx, ax, az, tmp2);
+        HELM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_axpy_d, dim3(nb), dim3(256), 0, s, out, tmp2, 2.0 * coef, N);
+    } else {
+        hipLaunchKernelGGL(k_axpy_d, dim3(nb), dim3(256), 0, s, out, tmp, -2.0 * coef, N);
+    }
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
+}
+
+// Gauss-Newton options with the defaults filled in and checked.
+static int gn_opts(const char* name, const fwi_gn_opts* g, double tol, const helm_op* op0, fwi_gn_opts* out) {
+    if (!g) return fail(HELM_EINVAL, "%s: NULL options", name);
+    *out = *g;
+    if (!(out->damping >= 0) || !std::isfinite(out->damping)) return fail(HELM_EINVAL, "%s: damping must be >= 0", name);
+    if (out->cg_iters < 0) return fail(HELM_EINVAL, "%s: cg_iters must be >= 0", name);
+    if (!(out->tol_sens > 0)) out->tol_sens = tol;
+    if (out->reg < FWI_REG_NONE || out->reg > FWI_REG_DIFF) return fail(HELM_EINVAL, "%s: unknown regulariser", name);
+    if (out->reg != FWI_REG_NONE) {
+        if (!(out->alpha >= 0) || !std::isfinite(out->alpha)) return fail(HELM_EINVAL, "%s: alpha must be >= 0", name);
+        if (!out->m_ref) return fail(HELM_EINVAL, "%s: the regulariser needs m_ref", name);
+    }
+    (void)op0;
+    return HELM_OK;
+}
+
+// cg_iters CG steps from x = 0 on (Re(J^H J) + alpha nabla^2 R + damping I) x =
+// sign * b (b float [N], device) into x_out (float, device); FP64 vector work,
+// dot products folded in a fixed order; the point-source fields are computed
+// on the first product (at tol) and reused; the Born and adjoint solves run at
+// g.tol_sens.  iters (host, may be NULL): [cg_iters][2][nfreq][nsrc], Born then
+// adjoint batch of each step (0 after an early stop).
+static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d,
+                      int nrec, const float* b, double sign, const fwi_gn_opts& g, double tol,
+                      const helm_solve_opts& o, float* x_out, double* resnorms, int* iters, hipStream_t s, Owned& own,
+                      const BornWork* fields = nullptr) {
+    const long N = ops[0]->n();
+    const int nfs = nfreq * nsrc;
+    double* x = own.get<double>(N);
+    double* r = own.get<double>(N);
+    double* p = own.get<double>(N);
+    double* ap = own.get<double>(N);
+    double* t1 = own.get<double>(N);
+    double* t2 = own.get<double>(N);
+    float* pf = own.get<float>(N);
+    float* hp = own.get<float>(N);
+    double* part = own.get<double>(CG_BLOCKS);
+    if (!x || !r || !p || !ap || !t1 || !t2 || !pf || !hp || !part)
+        return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    BornWork W;
+    int rc;
+    if (fields)
+        W = *fields;   // the point-source fields are already in W.u
+    else if ((rc = born_alloc(name, own, N, nfs, (long)nfs * nrec, W)))
+        return rc;
+    if (iters) std::fill(iters, iters + (size_t)g.cg_iters * 2 * nfs, 0);
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    HELM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    hipLaunchKernelGGL(k_f2d_scaled, dim3(nb), dim3(256), 0, s, b, sign, N, r);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipMemcpyAsync(p, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    double rr;
+    if ((rc = dot_d(r, r, N, part, &rr, s))) return rc;
+    if (resnorms) resnorms[0] = std::sqrt(rr);
+    int worst = HELM_OK;
+    std::vector<int> it3(3 * (size_t)nfs);
+    for (int k = 0; k < g.cg_iters; ++k) {
+        if (rr == 0) {   // b = 0 or an exact solution: the remaining steps change nothing
+            if (resnorms)
+                for (int q = k + 1; q <= g.cg_iters; ++q) resnorms[q] = 0;
+            break;
+        }
+        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, p, N, pf);
+        HELM_CHECK_LAUNCH();
+        const bool have_u = fields != nullptr || k > 0;
+        rc = born_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, pf, nullptr, nullptr, hp, tol, g.tol_sens, o,
+                       iters ? it3.data() : nullptr, s, W, have_u);
+        if (rc < 0) return rc;
+        worst = std::max(worst, rc);
+        if (iters) {
+            // born_core's batches: [forward,] Born, adjoint
+            const int* src = it3.data() + (have_u ? 0 : nfs);
+            std::copy(src, src + 2 * (size_t)nfs, iters + (size_t)k * 2 * nfs);
+        }
+        hipLaunchKernelGGL(k_cg_ap, dim3(nb), dim3(256), 0, s, hp, p, g.damping, N, ap);
+        HELM_CHECK_LAUNCH();
+        if (g.reg != FWI_REG_NONE && g.alpha > 0 &&
+            (rc = reg_hess_add(ops[0], g.reg, g.alpha, p, ap, t1, t2, s)))
+            return rc;
+        double pap;
+        if ((rc = dot_d(p, ap, N, part, &pap, s))) return rc;
+        if (!(pap > 0)) return fail(HELM_ENAN, "%s: p.Ap = %g at step %d (the system is not positive definite)",
+                                    name, pap, k);
+        const double step = rr / pap;
+        hipLaunchKernelGGL(k_cg_xr, dim3(nb), dim3(256), 0, s, x, r, p, ap, step, N);
+        HELM_CHECK_LAUNCH();
+        double rr_new;
+        if ((rc = dot_d(r, r, N, part, &rr_new, s))) return rc;
+        if (resnorms) resnorms[k + 1] = std::sqrt(rr_new);
+        hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(256), 0, s, p, r, rr_new / rr, N);
+        HELM_CHECK_LAUNCH();
+        rr = rr_new;
+    }
+    hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, x, N, x_out);
+    HELM_CHECK_LAUNCH();
+    HELM_HIP(hipStreamSynchronize(s));
+    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}
+
 }  // namespace
 }  // namespace helm
 
@@ -401,58 +656,61 @@ using namespace helm;
 extern "C" int fwi_misfit_grad(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
                                int nrec, const void* dobs, double tol, const helm_solve_opts* opt, double* misfit,
                                float* grad, int* iters, void* stream) {
+    const char* name = "fwi_misfit_grad";
     if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit || !grad)
-        return fail(HELM_EINVAL, "fwi_misfit_grad: bad arguments");
-    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad: tol must be positive");
-    int rc = check_args("fwi_misfit_grad", ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
+    hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, s, own);
     if (rc) return rc;
     helm_solve_opts o;
-    if ((rc = solve_opts(opt, "fwi_misfit_grad", &o))) return rc;
+    if ((rc = solve_opts(opt, name, &o))) return rc;
 
-    hipStream_t s = (hipStream_t)stream;
     const long N = ops[0]->n();
     const int nfs = nfreq * nsrc;
-    Owned own;
     c64* rhs = own.get<c64>((size_t)nfs * N);
     int* src_d = own.get<int>(nsrc);
     int* rec_d = own.get<int>(nrec);
-    if (!rhs || !src_d || !rec_d) return fail(HELM_ENOMEM, "fwi_misfit_grad: workspace allocation failed");
+    if (!rhs || !src_d || !rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemsetAsync(rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
     const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
     hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, rhs);
     HELM_CHECK_LAUNCH();
-    return misfit_grad_core(ops, nfreq, nsrc, rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, iters, s,
-                            own);
+    return misfit_grad_core(name, ops, nfreq, nsrc, rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad,
+                            iters, s, own);
 }
 
 extern "C" int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
                                        const float* X, int p, const int* rec_idx, int nrec, const void* dobs,
                                        double tol, const helm_solve_opts* opt, double* misfit, float* grad,
                                        int* iters, void* stream) {
+    const char* name = "fwi_misfit_grad_encoded";
     if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !X || p <= 0 || !rec_idx || nrec <= 0 || !dobs || !misfit ||
         !grad)
-        return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: bad arguments");
-    if (!(tol > 0)) return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: tol must be positive");
-    int rc = check_args("fwi_misfit_grad_encoded", ops, nfreq, src_idx, nsrc, rec_idx, nrec);
-    if (rc) return rc;
+        return fail(HELM_EINVAL, "%s: bad arguments", name);
+    if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
     for (long q = 0; q < (long)nsrc * p; ++q)
-        if (!std::isfinite(X[q])) return fail(HELM_EINVAL, "fwi_misfit_grad_encoded: X has a non-finite entry");
-    helm_solve_opts o;
-    if ((rc = solve_opts(opt, "fwi_misfit_grad_encoded", &o))) return rc;
-
+        if (!std::isfinite(X[q])) return fail(HELM_EINVAL, "%s: X has a non-finite entry", name);
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
     hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, s, own);
+    if (rc) return rc;
+    helm_solve_opts o;
+    if ((rc = solve_opts(opt, name, &o))) return rc;
+
     const long N = ops[0]->n();
     const int nfp = nfreq * p;
-    Owned own;
     c64* rhs = own.get<c64>((size_t)nfp * N);
     c64* dx = own.get<c64>((size_t)nfp * nrec);
     float* X_d = own.get<float>((size_t)nsrc * p);
     int* src_d = own.get<int>(nsrc);
     int* rec_d = own.get<int>(nrec);
-    if (!rhs || !dx || !X_d || !src_d || !rec_d)
-        return fail(HELM_ENOMEM, "fwi_misfit_grad_encoded: workspace allocation failed");
+    if (!rhs || !dx || !X_d || !src_d || !rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemcpyAsync(X_d, X, sizeof(float) * (size_t)nsrc * p, hipMemcpyHostToDevice, s));
@@ -465,7 +723,7 @@ extern "C" int fwi_misfit_grad_encoded(const helm_op_t* ops, int nfreq, const in
     hipLaunchKernelGGL(k_encode_data, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const c64*)dobs, X_d,
                        nsrc, p, nrec, total, dx);
     HELM_CHECK_LAUNCH();
-    return misfit_grad_core(ops, nfreq, p, rhs, dx, rec_d, nrec, tol, o, 1.0 / p, misfit, grad, iters, s, own);
+    return misfit_grad_core(name, ops, nfreq, p, rhs, dx, rec_d, nrec, tol, o, 1.0 / p, misfit, grad, iters, s, own);
 }
 
 // Shared set-up of the three linearised entry points.
@@ -475,21 +733,22 @@ static int born_entry(const char* name, const helm_op_t* ops, int nfreq, const i
     if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0)
         return fail(HELM_EINVAL, "%s: bad arguments", name);
     if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
-    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
+    hipStream_t s = (hipStream_t)stream;
+    Owned own;
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, s, own);
     if (rc) return rc;
     helm_solve_opts o;
     if ((rc = solve_opts(opt, name, &o))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    Owned own;
     int* src_d = own.get<int>(nsrc);
     int* rec_d = own.get<int>(nrec);
     if (!src_d || !rec_d) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
     HELM_HIP(hipMemcpyAsync(src_d, src_idx, sizeof(int) * nsrc, hipMemcpyHostToDevice, s));
     HELM_HIP(hipMemcpyAsync(rec_d, rec_idx, sizeof(int) * nrec, hipMemcpyHostToDevice, s));
     BornWork W;
-    if ((rc = born_alloc(own, ops[0]->n(), nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
-    return born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, dm, (const c64*)dd, (c64*)jdm, out, tol, o, iters, s, W,
-                     false);
+    if ((rc = born_alloc(name, own, ops[0]->n(), nfreq * nsrc, (long)nfreq * nsrc * nrec, W))) return rc;
+    return born_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, dm, (const c64*)dd, (c64*)jdm, out, tol, tol, o,
+                     iters, s, W, false);
 }
 
 extern "C" int fwi_born(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
@@ -516,93 +775,17 @@ extern "C" int fwi_gn_hessvec(const helm_op_t* ops, int nfreq, const int* src_id
                       iters, stream);
 }
 
-// cg_iters CG steps from x = 0 on (Re(J^H J) + damping I) x = sign * b (b float
-// [N], device) into x_out (float, device); FP64 vector work, dot products
-// folded in a fixed order; the point-source fields are computed on the first
-// product and reused.
-static int gn_cg_core(const char* name, const helm_op_t* ops, int nfreq, int nsrc, const int* src_d, const int* rec_d,
-                      int nrec, const float* b, double sign, double damping, int cg_iters, double tol,
-                      const helm_solve_opts& o, float* x_out, double* resnorms, hipStream_t s, Owned& own,
-                      const BornWork* fields = nullptr) {
-    const long N = ops[0]->n();
-    double* x = own.get<double>(N);
-    double* r = own.get<double>(N);
-    double* p = own.get<double>(N);
-    double* ap = own.get<double>(N);
-    float* pf = own.get<float>(N);
-    float* hp = own.get<float>(N);
-    double* part = own.get<double>(CG_BLOCKS);
-    if (!x || !r || !p || !ap || !pf || !hp || !part) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
-    BornWork W;
-    int rc;
-    if (fields)
-        W = *fields;   // the point-source fields are already in W.u
-    else if ((rc = born_alloc(own, N, nfreq * nsrc, (long)nfreq * nsrc * nrec, W)))
-        return rc;
-    std::vector<double> hpart(CG_BLOCKS);
-    auto dot = [&](const double* a, const double* c, double* result) -> int {
-        hipLaunchKernelGGL(k_cg_dot, dim3(CG_BLOCKS), dim3(256), 0, s, a, c, N, part);
-        HELM_CHECK_LAUNCH();
-        HELM_HIP(hipMemcpyAsync(hpart.data(), part, sizeof(double) * CG_BLOCKS, hipMemcpyDeviceToHost, s));
-        HELM_HIP(hipStreamSynchronize(s));
-        double acc = 0;
-        for (int i = 0; i < CG_BLOCKS; ++i) acc += hpart[i];
-        *result = acc;
-        return HELM_OK;
-    };
-    const unsigned nb = (unsigned)((N + 255) / 256);
-    HELM_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, s));
-    hipLaunchKernelGGL(k_f2d_scaled, dim3(nb), dim3(256), 0, s, b, sign, N, r);
-    HELM_CHECK_LAUNCH();
-    HELM_HIP(hipMemcpyAsync(p, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    double rr;
-    if ((rc = dot(r, r, &rr))) return rc;
-    if (resnorms) resnorms[0] = std::sqrt(rr);
-    int worst = HELM_OK;
-    for (int k = 0; k < cg_iters; ++k) {
-        if (rr == 0) {   // b = 0 or an exact solution: the remaining steps change nothing
-            if (resnorms)
-                for (int q = k + 1; q <= cg_iters; ++q) resnorms[q] = 0;
-            break;
-        }
-        hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, p, N, pf);
-        HELM_CHECK_LAUNCH();
-        rc = born_core(ops, nfreq, nsrc, src_d, rec_d, nrec, pf, nullptr, nullptr, hp, tol, o, nullptr, s, W,
-                       fields != nullptr || k > 0);
-        if (rc < 0) return rc;
-        worst = std::max(worst, rc);
-        hipLaunchKernelGGL(k_cg_ap, dim3(nb), dim3(256), 0, s, hp, p, damping, N, ap);
-        HELM_CHECK_LAUNCH();
-        double pap;
-        if ((rc = dot(p, ap, &pap))) return rc;
-        if (!(pap > 0)) return fail(HELM_ENAN, "%s: p.Ap = %g at step %d (the system is not positive definite)",
-                                    name, pap, k);
-        const double alpha = rr / pap;
-        hipLaunchKernelGGL(k_cg_xr, dim3(nb), dim3(256), 0, s, x, r, p, ap, alpha, N);
-        HELM_CHECK_LAUNCH();
-        double rr_new;
-        if ((rc = dot(r, r, &rr_new))) return rc;
-        if (resnorms) resnorms[k + 1] = std::sqrt(rr_new);
-        hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(256), 0, s, p, r, rr_new / rr, N);
-        HELM_CHECK_LAUNCH();
-        rr = rr_new;
-    }
-    hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, x, N, x_out);
-    HELM_CHECK_LAUNCH();
-    HELM_HIP(hipStreamSynchronize(s));
-    return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
-}
-
 // Shared argument checks and source/receiver upload of the Gauss-Newton entry points.
 static int gn_setup(const char* name, const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc,
-                    const int* rec_idx, int nrec, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
-                    helm_solve_opts* o, int** src_d, int** rec_d, hipStream_t s, Owned& own) {
-    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0 || cg_iters < 0)
+                    const int* rec_idx, int nrec, const fwi_gn_opts* gopt, double tol, const helm_solve_opts* opt,
+                    fwi_gn_opts* g, helm_solve_opts* o, int** src_d, int** rec_d, hipStream_t s, Owned& own,
+                    const float* m = nullptr) {
+    if (!ops || nfreq <= 0 || !src_idx || nsrc <= 0 || !rec_idx || nrec <= 0)
         return fail(HELM_EINVAL, "%s: bad arguments", name);
-    if (!(damping >= 0) || !std::isfinite(damping)) return fail(HELM_EINVAL, "%s: damping must be >= 0", name);
     if (!(tol > 0)) return fail(HELM_EINVAL, "%s: tol must be positive", name);
-    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec);
+    int rc = check_args(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, s, own, m);
     if (rc) return rc;
+    if ((rc = gn_opts(name, gopt, tol, ops[0], g))) return rc;
     if ((rc = solve_opts(opt, name, o))) return rc;
     *src_d = own.get<int>(nsrc);
     *rec_d = own.get<int>(nrec);
@@ -613,58 +796,91 @@ static int gn_setup(const char* name, const helm_op_t* ops, int nfreq, const int
 }
 
 extern "C" int fwi_gn_cg(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx, int nrec,
-                         const float* b, double damping, int cg_iters, double tol, const helm_solve_opts* opt,
-                         float* x_out, double* resnorms, void* stream) {
+                         const float* b, const fwi_gn_opts* gopt, double tol, const helm_solve_opts* opt,
+                         float* x_out, double* resnorms, int* iters, void* stream) {
     const char* name = "fwi_gn_cg";
     if (!b || !x_out) return fail(HELM_EINVAL, "%s: bad arguments", name);
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
     hipStream_t s = (hipStream_t)stream;
     Owned own;
+    fwi_gn_opts g;
     helm_solve_opts o;
     int *src_d = nullptr, *rec_d = nullptr;
-    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, damping, cg_iters, tol, opt, &o, &src_d, &rec_d,
-                      s, own);
+    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, gopt, tol, opt, &g, &o, &src_d, &rec_d, s, own);
     if (rc) return rc;
-    return gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, b, 1.0, damping, cg_iters, tol, o, x_out, resnorms,
-                      s, own);
+    return gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, b, 1.0, g, tol, o, x_out, resnorms, iters, s, own);
 }
 
 extern "C" int fwi_gn_step(const helm_op_t* ops, int nfreq, const int* src_idx, int nsrc, const int* rec_idx,
-                           int nrec, const void* dobs, const float* m, double damping, int cg_iters, double mu,
-                           double tol, const helm_solve_opts* opt, float* m_new, double* misfit, float* grad,
-                           double* resnorms, void* stream) {
+                           int nrec, const void* dobs, const float* m, const fwi_gn_opts* gopt, double mu, double tol,
+                           const helm_solve_opts* opt, float* m_new, double* misfit, double* reg_value, float* grad,
+                           double* resnorms, int* iters, void* stream) {
     const char* name = "fwi_gn_step";
     if (!dobs || !m || !m_new || !misfit || !grad || !std::isfinite(mu))
         return fail(HELM_EINVAL, "%s: bad arguments", name);
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
     hipStream_t s = (hipStream_t)stream;
     Owned own;
+    fwi_gn_opts g;
     helm_solve_opts o;
     int *src_d = nullptr, *rec_d = nullptr;
-    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, damping, cg_iters, tol, opt, &o, &src_d, &rec_d,
-                      s, own);
+    int rc = gn_setup(name, ops, nfreq, src_idx, nsrc, rec_idx, nrec, gopt, tol, opt, &g, &o, &src_d, &rec_d, s, own,
+                      m);
     if (rc) return rc;
     const long N = ops[0]->n();
     const int nfs = nfreq * nsrc;
-    // misfit and gradient at m (the operators' model)
+    const unsigned nb = (unsigned)((N + 255) / 256);
     BornWork W;
-    if ((rc = born_alloc(own, N, nfs, (long)nfs * nrec, W))) return rc;
+    if ((rc = born_alloc(name, own, N, nfs, (long)nfs * nrec, W))) return rc;
     float* dm = own.get<float>(N);
-    if (!dm) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    double* regg = own.get<double>(N);
+    double* d = own.get<double>(N);
+    double* t = own.get<double>(N);
+    double* part = own.get<double>(CG_BLOCKS);
+    if (!dm || !regg || !d || !t || !part) return fail(HELM_ENOMEM, "%s: workspace allocation failed", name);
+    // regulariser value and alpha dR/dm at m (FP64), added to the data gradient
+    double rv = 0;
+    const bool reg = g.reg != FWI_REG_NONE;
+    if (reg) {
+        hipLaunchKernelGGL(k_model_diff, dim3(nb), dim3(256), 0, s, m, g.m_ref, N, d);
+        HELM_CHECK_LAUNCH();
+        const double ax = 1.0 / (ops[0]->hx * ops[0]->hx), az = 1.0 / (ops[0]->hz * ops[0]->hz);
+        hipLaunchKernelGGL(k_reg_lap, dim3(nb), dim3(256), 0, s, d, ops[0]->nz, ops[0]->nx, ax, az, t);
+        HELM_CHECK_LAUNCH();
+        if (g.reg == FWI_REG_HIGH) {
+            if ((rc = dot_d(t, t, N, part, &rv, s))) return rc;             // ||Lap d||^2
+        } else {
+            if ((rc = dot_d(d, t, N, part, &rv, s))) return rc;             // ||grad d||^2 = -d.Lap d
+            rv = -rv;
+        }
+        HELM_HIP(hipMemsetAsync(regg, 0, sizeof(double) * N, s));
+        if ((rc = reg_hess_add(ops[0], g.reg, g.alpha, d, regg, t, W.gacc, s))) return rc;   // alpha dR/dm = alpha H_R d
+    }
+    if (reg_value) *reg_value = rv;
     HELM_HIP(hipMemsetAsync(W.rhs, 0, sizeof(c64) * (size_t)nfs * N, s));
     const float amp = (float)(1.0 / (ops[0]->hx * ops[0]->hz));
     hipLaunchKernelGGL(k_point_sources, dim3((nfs + 255) / 256), dim3(256), 0, s, src_d, nsrc, nfs, N, amp, W.rhs);
     HELM_CHECK_LAUNCH();
-    // the gradient's forward solves leave the point-source fields in W.u for the CG
-    rc = misfit_grad_core(ops, nfreq, nsrc, W.rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad, nullptr,
-                          s, own, W.u);
+    // misfit and gradient at m: the forward fields stay in W.u for the CG, the
+    // adjoint fields use W.w (free until the CG needs it)
+    rc = misfit_grad_core(name, ops, nfreq, nsrc, W.rhs, (const c64*)dobs, rec_d, nrec, tol, o, 1.0, misfit, grad,
+                          iters, s, own, W.u, W.w, reg ? regg : nullptr);
     if (rc < 0) return rc;
     int worst = rc;
     // dm from CG on -grad, then m_new = m + mu dm
-    rc = gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, grad, -1.0, damping, cg_iters, tol, o, dm, resnorms, s,
-                    own, &W);
+    rc = gn_cg_core(name, ops, nfreq, nsrc, src_d, rec_d, nrec, grad, -1.0, g, tol, o, dm, resnorms,
+                    iters ? iters + 2 * (size_t)nfs : nullptr, s, own, &W);
     if (rc < 0) return rc;
     worst = std::max(worst, rc);
-    hipLaunchKernelGGL(k_model_update, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, m, dm, mu, N, m_new);
+    hipLaunchKernelGGL(k_model_update, dim3(nb), dim3(256), 0, s, m, dm, mu, N, m_new);
     HELM_CHECK_LAUNCH();
     HELM_HIP(hipStreamSynchronize(s));
     return worst == HELM_NOT_CONVERGED ? HELM_NOT_CONVERGED : HELM_OK;
+}
+
+extern "C" int fwi_release_workspace(void) {
+    std::lock_guard<std::recursive_mutex> lk(g_fwi_mutex);
+    HELM_HIP(hipDeviceSynchronize());
+    g_pool.release();
+    return HELM_OK;
 }

@@ -58,6 +58,24 @@ __global__ void k_conj_copy(const cx<T>* __restrict__ a, cx<T>* __restrict__ b, 
     if (t < n) b[t] = conj(a[t]);
 }
 
+// Bilinear resampling of a nodal field onto an mz x mx grid of the same extent
+// (output node (I, K) sits at input coordinates I (nz-1)/(mz-1), K (nx-1)/(mx-1)).
+__global__ void k_resample(const float* __restrict__ in, int nz, int nx, float* __restrict__ out, int mz, int mx) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)mz * mx) return;
+    const int I = (int)(t / mx), K = (int)(t - (long)I * mx);
+    const double z = mz > 1 ? (double)I * (nz - 1) / (mz - 1) : 0.0;
+    const double x = mx > 1 ? (double)K * (nx - 1) / (mx - 1) : 0.0;
+    int i0 = (int)z, k0 = (int)x;
+    if (i0 > nz - 2) i0 = nz > 1 ? nz - 2 : 0;
+    if (k0 > nx - 2) k0 = nx > 1 ? nx - 2 : 0;
+    const double a = nz > 1 ? z - i0 : 0.0, b = nx > 1 ? x - k0 : 0.0;
+    const int i1 = nz > 1 ? i0 + 1 : i0, k1 = nx > 1 ? k0 + 1 : k0;
+    const double v = (1 - a) * ((1 - b) * in[(long)i0 * nx + k0] + b * in[(long)i0 * nx + k1]) +
+                     a * ((1 - b) * in[(long)i1 * nx + k0] + b * in[(long)i1 * nx + k1]);
+    out[t] = (float)v;
+}
+
 template <typename T>
 static int conj_copy(const cx<T>* a, cx<T>* b, long n, hipStream_t s) {
     if (n == 0) return HELM_OK;
@@ -240,10 +258,12 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
                                          gr.r0, sizeof(T) == 8, s);
                     break;
                 case HELM_PRECOND_CNN_VU: {
+                    // a right-hand side whose network output is not finite gets
+                    // e0 = 0, i.e. M_VU = V_SL for that step
                     cx<T>* e0 = (cx<T>*)W.cnn_e0.p;
                     cx<T>* res = (cx<T>*)W.cnn_res.p;
                     r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)e0, gr.n, a.st,
-                                         gr.r0, sizeof(T) == 8, s);
+                                         gr.r0, sizeof(T) == 8, s, true);
                     if (r) return r;
                     r = launch_residual_vs_e0<T>(ga[gi], gr.n, a, j, e0, res, s);
                     if (r) return r;
@@ -500,6 +520,15 @@ int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream) {
     w.rb = (c128*)W.mg[2 * MAX_LEVELS + 1].p;
     w.xw = (c128*)W.mg[2 * MAX_LEVELS + 2].p;
     return launch_vcycle<float>(op, (const c64*)f, nullptr, 0, (c64*)e, nullptr, nrhs, nullptr, 0, w, s);
+}
+
+int helm_resample(const float* in, int nz, int nx, float* out, int mz, int mx, void* stream) {
+    if (!in || !out || nz < 1 || nx < 1 || mz < 1 || mx < 1) return fail(HELM_EINVAL, "helm_resample: bad arguments");
+    const long n = (long)mz * mx;
+    hipLaunchKernelGGL(k_resample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, in, nz, nx,
+                       out, mz, mx);
+    HELM_CHECK_LAUNCH();
+    return HELM_OK;
 }
 
 int helm_coarse_roots(helm_op_t op, double* roots, int* n) {

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import bf16_storage as BS
 from helpers import medium, rand_c, relerr
 from oracle import krylov as kr
 from oracle import multigrid as mg
@@ -58,7 +59,7 @@ def test_forward_parity(gpu, nz, nx):
     enc = U.encoder_input(med.kappa2, med.gamma, med.omega, med.h, med.h)
     ref, _ = U.network_forward(theta, enc, rin.astype(np.float64), W, DR)
     print("rel err", relerr(out, ref))
-    assert relerr(out, ref) <= 3e-2
+    assert relerr(out, ref) <= 2e-2      # BF16 storage alone: 1.3% on this shape
 
 
 @pytest.mark.parametrize("nz,nx,B", [(32, 32, 1), (48, 80, 3), (40, 56, 2)])
@@ -76,7 +77,7 @@ def test_forward_parity_full_width(gpu, nz, nx, B):
     enc = U.encoder_input(med.kappa2, med.gamma, med.omega, med.h, med.h)
     ref, _ = U.network_forward(theta, enc, rin.astype(np.float64), widths, 2)
     print("rel err", relerr(out, ref))
-    assert relerr(out, ref) <= 3e-2
+    assert relerr(out, ref) <= 2e-2      # BF16 storage alone: 1.2% on the 48 x 80 shape
 
 
 def test_loss_gradient_parity(gpu):
@@ -93,13 +94,17 @@ def test_loss_gradient_parity(gpu):
     enc = U.encoder_input(med.kappa2, med.gamma, med.omega, med.h, med.h)
     L, gref = T.loss_and_grad(theta, enc, r.astype(np.complex128), e.astype(np.complex128), med.h, med.h, W, DR)
     cos = g @ gref / np.linalg.norm(g) / np.linalg.norm(gref)
-    print("loss", loss, L, "grad rel", relerr(g, gref), "cos", cos)
-    # BF16 activations and weights through ~40 layers and their mirror: the
-    # forward alone differs by ~1.3% (the same as rounding the oracle's storage
-    # to BF16); the backward doubles the chain
+    _, gemu = BS.loss_and_grad(theta, enc, r.astype(np.complex128), e.astype(np.complex128), med.h, med.h, W, DR)
+    print("loss", loss, L, "grad rel", relerr(g, gref), "cos", cos, "vs BF16-storage oracle", relerr(g, gemu),
+          "floor", relerr(gemu, gref))
+    # BF16 weights, activations and masked gradients through ~40 layers and
+    # their mirror: the oracle with only its storage rounded to BF16 is 6.2%
+    # (cosine 0.9981) from the FP64 gradient on this very case
+    # (test_bf16_floor); the GPU lands at that floor (5.5-6.2%, cosine
+    # 0.9981-0.9985 with the kernel choices of different runs)
     assert abs(loss - L) <= 2e-2 * L
     assert relerr(g, gref) <= 8e-2
-    assert cos >= 0.998
+    assert cos >= 0.997
 
 
 def test_adam_step_parity(gpu):
@@ -290,3 +295,54 @@ def test_one_iteration_closed_form_cnn_vu(gpu, bscale):
     ref = x0 + y * z
     print("closed form rel", relerr(x1.cpu().numpy(), ref))
     assert relerr(x1.cpu().numpy() - x0, ref - x0) <= 1e-4
+
+
+def test_non_finite_network_output_falls_back_to_vcycle(gpu):
+    """A network whose output is NaN (a poisoned head bias): inside M_VU every
+    affected right-hand side falls back to e0 = 0, i.e. M_VU = V_SL, so
+    CNN-FGMRES(10) converges like MG-GMRES(10) instead of breaking down."""
+    n = 64
+    med = medium(n, n, seed=20)
+    H = setup(med)
+    net, theta = small_net(seed=13)
+    theta = theta.astype(np.float32)
+    theta[-1] = np.nan                     # bias of the head's second output channel
+    api.cnn_set_params(net, theta)
+    b = rand_c((3, n, n), 8).astype(np.complex64)
+    bt = torch.tensor(b, device="cuda")
+    e = api.cnn_precond_apply(net, H, bt).cpu().numpy()
+    assert np.isnan(e).any()               # the raw preconditioner keeps the NaN
+    x, it, rr, st, code = api.helm_solve(H, bt, tol=1e-6, precond="cnn_vu", maxit=800, net=net, restart=10)
+    _, itm, _, _, cm = api.helm_solve(H, bt, tol=1e-6, precond="mg", maxit=800, restart=10)
+    print("poisoned network: cnn_vu iterations", it, "mg(10)", itm)
+    assert code == 0 and np.all(st == 0) and cm == 0
+    coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
+    assert np.all(op.relres(coef, x.cpu().numpy(), b.astype(np.complex128), med.h, med.h) <= 1e-6)
+    assert np.all(np.abs(it - itm) <= 2)
+
+
+def test_trained_network_beats_multigrid(gpu):
+    """What the learned part gains: a network trained by the library's own
+    kernels on eq. (4.3) pairs of a 64 x 64 layered medium makes CNN-FGMRES(10)
+    need fewer iterations than MG-GMRES(20) on surface sources of that medium
+    (the sources are not training data), and fewer than the untrained network."""
+    from paper_2405_17696_amd import synth
+    n = 64
+    rng = np.random.default_rng(61)
+    c = synth.velocity_layered(n, n, rng)
+    med = synth.medium_from_velocity(c)
+    med.kappa2 = np.asarray(med.kappa2, np.float32).astype(np.float64)
+    med.gamma = np.asarray(med.gamma, np.float32).astype(np.float64)
+    H = setup(med)
+    src = synth.point_sources(n, n, synth.surface_positions(n, 8), h=med.h)
+    b = torch.tensor(src, dtype=torch.complex64, device="cuda")
+    net = api.cnn_create(seed=1)
+    _, it0, _, _, c0 = api.helm_solve(H, b, tol=1e-6, precond="cnn_vu", maxit=1000, net=net, restart=10)
+    _, itm, _, _, cm = api.helm_solve(H, b, tol=1e-6, precond="mg", maxit=1000, restart=20)
+    print("training 64x64 network", flush=True)
+    for rnd, lr in enumerate((1e-3, 1e-3, 5e-4, 2.5e-4)):
+        api.cnn_precond_train(net, H, npairs=1024, batch=16, steps=500, lr=lr, seed=100 + rnd)
+    x, it1, rr, st, c1 = api.helm_solve(H, b, tol=1e-6, precond="cnn_vu", maxit=1000, net=net, restart=10)
+    print("iterations: untrained", it0.mean(), "trained", it1.mean(), "MG-GMRES(20)", itm.mean())
+    assert c0 == 0 and cm == 0 and c1 == 0
+    assert it1.mean() < itm.mean() and it1.mean() < it0.mean()

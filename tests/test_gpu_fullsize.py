@@ -51,10 +51,18 @@ def c2(gpu):
 def test_bench_workload_full_size(c2, precond, restart):
     med, src, H, coef = c2
     print("full-size c2", precond, flush=True)
-    net = api.cnn_create(seed=1) if precond != "mg" else None
+    net = None
+    if precond != "mg":
+        # a network moved well away from its near-zero initial map by 300 Adam
+        # steps on eq. (4.3) pairs of this medium (the solver's first layer,
+        # context convolutions, fused residual blocks and head all carry
+        # trained weights)
+        net = api.cnn_create(seed=1)
+        api.cnn_precond_train(net, H, npairs=512, batch=16, steps=300, lr=1e-3, seed=7)
     b = torch.tensor(src, dtype=torch.complex64, device="cuda")
     x, it, rr, st, code = api.helm_solve(H, b, tol=1e-6, precond=precond, maxit=3000, net=net, restart=restart,
                                          use_graph=True)
+    print("iterations", it.mean(), it.max())
     assert code == 0 and np.all(st == 0)
     xh = x.cpu().numpy()
     rel = op.relres(coef, xh, src.astype(np.complex128), med.h, med.h)

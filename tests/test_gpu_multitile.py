@@ -1,0 +1,111 @@
+"""The persistent convolution kernels on grids with more tiles than resident
+blocks, so that every block walks several tiles (the tile loop, the next-tile
+prefetch and the LDS reuse between tiles), and the preconditioner with
+full-width He-initialised weights at the bench's 256 x 256 size, against the
+oracle.  At B = 4 and 256 x 256 a level-0 layer has 1024 16 x 16 tiles (1444
+14 x 14 residual-block tiles), several per block at the occupancy of these
+kernels on 256 compute units."""
+import numpy as np
+import pytest
+import torch
+
+import bf16_storage as B
+from helpers import f32, rand_c, relerr
+from oracle import unet as U
+from paper_2405_17696_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+CK_PERS = 0     # the persistent halo kernel's id for helm_conv_force
+
+
+def bf(x):
+    return B.bf16(x)
+
+
+def rnd(shape, seed, scale=1.0):
+    return bf(scale * np.random.default_rng(seed).standard_normal(shape))
+
+
+@pytest.mark.parametrize("c2,bcast", [(0, False), (32, True)])
+def test_persistent_conv_many_tiles_per_block(gpu, c2, bcast):
+    Bn, H, W_ = 4, 256, 256
+    print("persistent conv multi-tile c2", c2, flush=True)
+    x1 = rnd((Bn, H, W_, 32), 31)
+    x2 = rnd((1, H, W_, c2), 32) if c2 else None
+    Wt = rnd((32, 3, 3, 32 + c2), 33, scale=np.sqrt(2.0 / (9 * (32 + c2))))
+    b = rnd((32,), 34, 0.1)
+    api.helm_conv_force(CK_PERS)
+    try:
+        y = api.cnn_layer_forward(0, 1, x1, Wt, b, x2=x2, bcast2=bcast, relu=True)
+    finally:
+        api.helm_conv_force(-1)
+    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])], axis=-1)
+    ref = np.maximum(U.conv3x3(x, Wt, b, 1), 0)
+    e = relerr(y, ref)
+    print("rel err", e)
+    assert e <= 1e-5
+    # every sample and every tile row/column is covered (a skipped tile leaves zeros or stale values)
+    for s in range(Bn):
+        for t in range(0, H, 16):
+            assert relerr(y[s, t:t + 16], ref[s, t:t + 16]) <= 1e-5
+
+
+def test_fused_resblock_many_tiles_per_block(gpu):
+    Bn, H, W_ = 4, 256, 256
+    print("resblock multi-tile", flush=True)
+    x = rnd((Bn, H, W_, 32), 41)
+    W1 = rnd((32, 3, 3, 32), 42, scale=np.sqrt(2.0 / 288))
+    W2 = rnd((32, 3, 3, 32), 43, scale=np.sqrt(2.0 / 288))
+    b1 = rnd((32,), 44, 0.1)
+    b2 = rnd((32,), 45, 0.1)
+    y = api.cnn_layer_resblock(x, W1, b1, W2, b2)
+    h = bf(np.maximum(U.conv3x3(x, W1, b1, 1), 0))
+    ref = x + U.conv3x3(h, W2, b2, 1)
+    e = relerr(y, ref)
+    print("rel err", e)
+    assert e <= 5e-3                                      # output stored in BF16
+    for s in range(Bn):
+        for t in range(0, H, 14):
+            assert relerr(y[s, t:t + 14], ref[s, t:t + 14]) <= 5e-3
+
+
+def test_precond_apply_full_width_full_size(gpu):
+    """M_net(r) at 256 x 256, batch 2, default widths, He-normal weights at full
+    scale (no damped head) and small random biases: the inference path with the
+    fused first layer + context convolution and the fused residual blocks, over
+    1024 level-0 tiles per launch."""
+    med, _ = synth.config2_medium()
+    k2, gam = f32(med.kappa2), f32(med.gamma)
+    widths = (32, 64, 128, 256)
+    layers = U.all_layers(widths, 2)
+    theta = U.init_params(layers, np.random.default_rng(51)).astype(np.float32)
+    o = 0
+    rng = np.random.default_rng(52)
+    for l in layers:
+        o += int(np.prod(l.wshape()))
+        theta[o:o + l.cout] = 0.05 * rng.standard_normal(l.cout)
+        o += l.cout
+    net = api.cnn_create(widths, seed=0, down_res=2)
+    api.cnn_set_params(net, theta)
+    theta = theta.astype(np.float64)
+    H = api.helm_setup(torch.tensor(k2, dtype=torch.float32, device="cuda"),
+                       torch.tensor(gam, dtype=torch.float32, device="cuda"), med.omega, med.h)
+    r = rand_c((2, 256, 256), 53).astype(np.complex64)
+    print("precond apply full size", flush=True)
+    e = api.cnn_precond_apply(net, H, torch.tensor(r, device="cuda")).cpu().numpy()
+    rr = r.astype(np.complex128)
+    ref = U.cnn_precond(theta, k2, gam, med.omega, med.h, med.h, rr, widths, 2)
+    orig = U.Net
+    U.Net = B.Bf16Net
+    try:
+        emu = U.cnn_precond(theta, k2, gam, med.omega, med.h, med.h, rr, widths, 2)
+    finally:
+        U.Net = orig
+    e64, eb = relerr(e, ref), relerr(e, emu)
+    print("rel err vs FP64", e64, "vs BF16-storage oracle", eb, "floor", relerr(emu, ref))
+    # BF16 storage alone moves this network's output by 1.2% on this case
+    # (the BF16-storage oracle above); P7's 2e-2 bound
+    assert e64 <= 2e-2
+    for s in range(2):
+        assert relerr(e[s], ref[s]) <= 2e-2

@@ -329,3 +329,21 @@ def test_regularised_gn_cg_and_step():
         assert rv == fwi.regulariser(kind, k2, mref, h)[0]
         # the step is a descent direction of the regularised objective
         assert np.sum((m_new - k2) * g) < 0
+
+
+def test_resample_bilinear():
+    """Identity on the same grid, exact on fields linear in the coordinates
+    (bilinear interpolation reproduces them), a hand-computed midpoint."""
+    rng = np.random.default_rng(45)
+    f = rng.standard_normal((9, 13))
+    assert np.allclose(fwi.resample_bilinear(f, 9, 13), f, atol=1e-15)
+    Z, X = np.meshgrid(np.arange(9.0), np.arange(13.0), indexing="ij")
+    lin = 0.3 + 0.5 * Z - 0.25 * X + 0.1 * Z * X          # bilinear, so reproduced exactly
+    r = fwi.resample_bilinear(lin, 17, 7)
+    z = np.arange(17) * 8 / 16
+    x = np.arange(7) * 12 / 6
+    Zr, Xr = np.meshgrid(z, x, indexing="ij")
+    assert np.allclose(r, 0.3 + 0.5 * Zr - 0.25 * Xr + 0.1 * Zr * Xr, atol=1e-12)
+    # 3 x 3 -> 5 x 5: node (1, 1) of the output sits at (0.5, 0.5): mean of the four corners
+    g = rng.standard_normal((3, 3))
+    assert abs(fwi.resample_bilinear(g, 5, 5)[1, 1] - g[:2, :2].mean()) < 1e-14
