@@ -132,6 +132,22 @@ int helm_vcycle(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
  * in and out must not overlap.
  */
 int helm_resample(const float* in, int nz, int nx, float* out, int mz, int mx, void* stream);
+/*
+ * helm_vcycle_noalloc -- helm_vcycle for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and result, with the cycle's scratch
+ * (coarse-level right-hand sides and corrections, coarsest-level FP64
+ * buffers: 2 x 8 B x nrhs x (N_1 + N_2) + 3 x 16 B x nrhs x N_2 for three
+ * levels, N_l = nodes of level l, each piece rounded up to 256 B) in a fixed
+ * device array of helm_vcycle_noalloc_max_bytes() = 32 MiB per GPU that the
+ * library holds until the process ends.  The call allocates nothing; it
+ * returns HELM_EINVAL when the scratch would exceed the array (512 KiB per
+ * right-hand side of a 256 x 256 grid: at most 64 of them per call).  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (other streams or threads) race and must not be issued.
+ */
+int helm_vcycle_noalloc(helm_op_t op, const void* f, void* e, int nrhs, void* stream);
+size_t helm_vcycle_noalloc_max_bytes(void);
 /* Roots of the coarsest-level polynomial, in application order (host, c128 [*n]). */
 int helm_coarse_roots(helm_op_t op, double* roots, int* n);
 

@@ -70,6 +70,8 @@ SIGNATURES = {
                              C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p]),
     "helm_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "helm_resample": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "helm_vcycle_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "helm_vcycle_noalloc_max_bytes": (C.c_size_t, []),
     "helm_coarse_roots": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "cnn_create": (C.c_int, [C.POINTER(CnnArch), C.c_uint64, C.POINTER(C.c_void_p)]),
     "cnn_destroy": (None, [C.c_void_p]),

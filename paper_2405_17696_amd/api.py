@@ -96,6 +96,16 @@ def helm_resample(f: torch.Tensor, mz: int, mx: int) -> torch.Tensor:
     return out
 
 
+def helm_vcycle_noalloc(op: HelmOp, f: torch.Tensor, e: torch.Tensor) -> torch.Tensor:
+    """e = V_SL(f) without any allocation in the library (fixed scratch array); e must be given."""
+    if f.dtype != torch.complex64 or e.dtype != torch.complex64 or e.numel() != f.numel():
+        raise TypeError("helm_vcycle_noalloc takes complex64 f and e of one size")
+    if f.numel() % op.n:
+        raise ValueError("f size is not a multiple of the grid size")
+    L.check(L.load().helm_vcycle_noalloc(op.handle, _ptr(f), _ptr(e), f.numel() // op.n, _stream()))
+    return e
+
+
 def helm_coarse_roots(op: HelmOp):
     import numpy as np
     lib = L.load()
