@@ -19,13 +19,26 @@ workload's and the best is kept.  Training throughput is reported in
 `training`.
 
 Other workloads (--workload), each one JSON line of measurements:
+  pretrain  the paper's initial training, scaled down: random linear
+      slowness-squared media on 128x128, 128x256 and 256x256 grids at 5-12
+      points per wavelength (--pretrain-steps Adam steps), then iteration
+      counts on media it was not trained on; --save-net keeps the network;
   c3  uneven batch: 3 grids x 3 frequencies x 64 sources (576 systems) in one
-      masked MG-GMRES(20) launch, eager and graph-replayed;
-  c4  retraining: network trained on the c2 medium, then retrained (200 Adam
-      steps, lr 1e-4, 2000 pairs) on the 5%-perturbed medium; FGMRES iteration
-      counts before / after / MG;
-  c5  FWI misfit gradient: 512x512, 128 sources, 128 receivers, 4 frequencies,
-      forward + adjoint solves through fwi_misfit_grad.
+      masked launch, CNN-FGMRES(10) with the pre-trained network (--net, or
+      pre-trained here) or MG-GMRES(20) (--c3-precond mg), eager and
+      graph-replayed;
+  c4  the paper's retraining regime: the pre-trained network on the
+      5%-perturbed layered medium, iteration counts before / after Alg. 2
+      (128 -> 1024 pairs) and plain retraining (2000 pairs, 200 steps, lr 1e-4),
+      and MG-GMRES;
+  c5  FWI on 512x512 (128 sources, 128 receivers, 4 frequencies): the misfit
+      gradient with MG-GMRES(20) and with CNN-FGMRES(10) (pre-trained network
+      retrained on the initial model), 16 simultaneous sources, Gauss-Newton CG
+      with the sensitivities at 1e-4, and Alg. 1 with the diffusion regulariser
+      and retraining after every window.
+The oracle leg (cpu_baseline) times the oracle's sparse direct solve (factor
+once, solve all 32 right-hand sides) on one host core and on all of them, and
+the iterative FP64 oracle on 4 right-hand sides.
 """
 from __future__ import annotations
 
@@ -52,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "pretrain"])
     ap.add_argument("--precond", default="cnn_vu", choices=["mg", "cnn_vu", "cnn"])
     ap.add_argument("--train-steps", type=int, default=16000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
@@ -72,6 +85,9 @@ def parse():
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
+    ap.add_argument("--pretrain-steps", type=int, default=6000,
+                    help="pretrain / c3 / c4: Adam steps of the pre-training on random linear media (no --net)")
+    ap.add_argument("--c3-precond", default="cnn_vu", choices=["mg", "cnn_vu"], help="c3: preconditioner")
     ap.add_argument("--tune-file", default=None,
                     help="load convolution kernel choices from this file if it exists, save them after the run")
     return ap.parse_args()
@@ -388,11 +404,64 @@ def main_c2(a):
     print(json.dumps(out))
 
 
+PRETRAIN_HALVINGS = (0.5, 0.75)   # fractions of the pre-training at which the learning rate halves
+
+
+def pretrained_net(api, a, log=True):
+    """The network of the paper's regime: loaded from --net, or pre-trained here
+    on random linear slowness-squared media (Sec. 4.1) on 128x128, 128x256 and
+    256x256 grids at 5-12 points per wavelength (a scaled-down version of the
+    paper's initial training)."""
+    from paper_2405_17696_amd import training
+    if a.net:
+        return api.cnn_load(a.net), None
+    net = api.cnn_create(seed=1)
+    api.helm_autotune(0)
+    k = a.pretrain_steps
+    info = training.pretrain(net, k, lr0=1e-3, halvings=tuple(int(f * k) for f in PRETRAIN_HALVINGS), seed=11,
+                             log=(lambda m: print(m, file=sys.stderr, flush=True)) if log else None)
+    api.helm_autotune(1)
+    if a.save_net:
+        api.cnn_save(net, a.save_net)
+    return net, info
+
+
+def main_pretrain(a):
+    """Pre-training alone, with the resulting network's iteration counts on
+    media it was not trained on: a linear medium, the 256x256 layered workload
+    medium (c2) and its perturbed version (c4), each at 10 points per
+    wavelength, against MG-GMRES(20)."""
+    import torch
+    from paper_2405_17696_amd import api, synth, training
+    net, info = pretrained_net(api, a)
+    t = lambda v: torch.tensor(np.asarray(v, np.float32), device="cuda")
+    med2, src = synth.config2_medium()
+    b = torch.tensor(src, dtype=torch.complex64, device="cuda")
+    k2l, gl, wl = training.random_linear_medium(np.random.default_rng(999), 256, 256, 10.0)
+    media = {"linear_256": (t(k2l), t(gl), wl, synth.H_DEFAULT), "c2_layered": (t(med2.kappa2), t(med2.gamma),
+                                                                                  med2.omega, med2.h)}
+    med4 = synth.config4_medium()
+    media["c4_perturbed"] = (t(med4.kappa2), t(med4.gamma), med4.omega, med4.h)
+    res = {}
+    for name, (k2, g, w, h) in media.items():
+        res[name] = {"cnn_vu": training.solve_iterations(net, k2, g, w, h, b, "cnn_vu", a.restart, a.maxit),
+                     "mg": training.solve_iterations(None, k2, g, w, h, b, "mg", 20, a.maxit)}
+        print(f"pretrained network on {name}: {res[name]}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "pre-training on random linear slowness-squared media (Sec. 4.1), scaled down",
+                      "pretraining": info, "iterations_10ppw_32_sources": res}))
+
+
 def main_c3(a):
+    """The uneven batch: 3 grids x 3 frequencies x 64 sources in one masked
+    FGMRES launch, with the pre-trained network (M_VU, FGMRES(10)) or
+    MG-GMRES(20); eager, then graph-replayed."""
     import torch
     from paper_2405_17696_amd import api, synth
     nsrc = a.sources or 64
     items = synth.config3_media(nsrc=nsrc)
+    pc = a.c3_precond
+    net, info = pretrained_net(api, a) if pc != "mg" else (None, None)
+    restart = a.restart if pc != "mg" else a.mg_restart
     ops, rhs_op, parts = [], [], []
     for k, (med, src) in enumerate(items):
         k2 = torch.tensor(med.kappa2, dtype=torch.float32, device="cuda")
@@ -405,8 +474,8 @@ def main_c3(a):
     for use_graph in (False, True):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, it, rr, st, code = api.helm_solve(ops, b, tol=1e-6, rhs_op=rhs_op, precond="mg", maxit=a.maxit,
-                                             restart=a.mg_restart, use_graph=use_graph)
+        x, it, rr, st, code = api.helm_solve(ops, b, tol=1e-6, rhs_op=rhs_op, precond=pc, maxit=a.maxit,
+                                             restart=restart, use_graph=use_graph, net=net)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         conv = int((st == 0).sum())
@@ -419,226 +488,202 @@ def main_c3(a):
                            "converged": int((st[sel] == 0).sum()), "systems": len(sel)})
         res["graph" if use_graph else "eager"] = {"seconds": dt, "converged": conv, "systems": len(rhs_op),
                                                  "converged_rhs_per_s": conv / dt, "groups": groups}
-        print(f"c3 {'graph' if use_graph else 'eager'} done in {dt:.1f} s", file=sys.stderr, flush=True)
+        print(f"c3 {'graph' if use_graph else 'eager'} done in {dt:.1f} s, {conv} converged", file=sys.stderr,
+              flush=True)
+        if a.no_graph:
+            break
+    name = f"CNN-FGMRES({restart}) with the pre-trained network" if pc != "mg" else f"MG-GMRES({restart})"
     print(json.dumps({"workload": "c3 uneven batch: 256x512, 384x768, 512x1024 x 5/8/12 ppw x "
-                                  f"{nsrc} sources, MG-GMRES({a.mg_restart}), tol 1e-6, maxit {a.maxit}",
-                      "systems": len(rhs_op), "node_rhs": int(b.numel()), "results": res}))
+                                  f"{nsrc} sources, {name}, tol 1e-6, maxit {a.maxit}",
+                      "systems": len(rhs_op), "node_rhs": int(b.numel()), "pretraining": info, "results": res}))
 
 
 def main_c4(a):
+    """The paper's regime (Sec. 4.1-4.2, Alg. 2): a network pre-trained on random
+    linear media meets the 5%-perturbed layered medium; iteration counts on the
+    workload's 32 surface sources before retraining, after Alg. 2 retraining
+    (128 eq. (4.3) pairs doubled over 3 data epochs to 1024, 4 passes, Adam lr
+    1e-4, batch 16) and after plain retraining (2000 pairs, 200 steps, lr
+    1e-4), each from the pre-trained weights, and MG-GMRES(20)."""
     import torch
-    from paper_2405_17696_amd import api, synth
+    from paper_2405_17696_amd import api, synth, training
     med2, src = synth.config2_medium()
     med4 = synth.config4_medium()
-    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    t = lambda v: torch.tensor(np.asarray(v, np.float32), device="cuda")
     b = torch.tensor(src, dtype=torch.complex64, device="cuda")
-    net, training = get_net(api, a, t(med2.kappa2), t(med2.gamma), med2)
-
-    def iters(pc, m, with_net=None):
-        op = api.helm_setup(t(m.kappa2), t(m.gamma), m.omega, m.h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, it, rr, st, code = api.helm_solve(op, b, tol=1e-6, precond=pc, maxit=a.maxit,
-                                             net=with_net if with_net is not None else net,
-                                             restart=a.restart if pc != "mg" else 20)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        op.close()
-        return {"iters_mean": float(it.mean()), "iters_max": int(it.max()), "converged": int((st == 0).sum()),
-                "seconds": dt}
-
-    before = iters("cnn_vu", med4)
-    if a.save_net is None:
-        api.cnn_save(net, "/tmp/_c4_pretrained.bin")
-        pre = "/tmp/_c4_pretrained.bin"
-    else:
-        pre = a.save_net
-    op4 = api.helm_setup(t(med4.kappa2), t(med4.gamma), med4.omega, med4.h)
+    net, info = pretrained_net(api, a)
+    pre = "/tmp/_c4_pretrained.bin"
+    api.cnn_save(net, pre)
+    k2, g = t(med4.kappa2), t(med4.gamma)
+    iters = lambda nn: training.solve_iterations(nn, k2, g, med4.omega, med4.h, b, "cnn_vu", a.restart, a.maxit)
+    before = iters(net)
+    print(f"c4 before retraining: {before}", file=sys.stderr, flush=True)
     variants = {}
-    for name, kw in (("plain", dict(npairs=2000, steps=200, lr=1e-4)),
-                     ("alg2", dict(npairs=128, steps=200, lr=1e-4, alg2_initial=128, alg2_data_epochs=3,
-                                   alg2_epochs=6))):
-        net = api.cnn_load(pre)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hist, dsz = api.cnn_precond_train(net, op4, batch=16, seed=4001, **kw)
-        torch.cuda.synchronize()
-        tr = time.perf_counter() - t0
-        variants[name] = {"retraining_seconds": tr, "steps": len(hist), "dataset": dsz,
-                          "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:])),
-                          "after": iters("cnn_vu", med4)}
-    for lr in (1e-4, 2.5e-5, 1e-5):
-        variants[f"plain_selected_lr{lr:g}"] = retrain_selected(api, pre, op4, med4, iters, a, lr=lr)
-    op4.close()
-    mg = iters("mg", med4)
-    print(json.dumps({"workload": "c4 retraining on the 5%-perturbed c2 medium: batch 16, 200 Adam steps, lr 1e-4; "
-                                  "plain = 2000 eq. (4.3) pairs, alg2 = Alg. 2 from 128 pairs, 3 data epochs, "
-                                  "plain_selected_lr* = plain at that learning rate with the weights scored every 25 steps "
-                                  "on validation sources and the best kept (the pre-retraining weights included)",
-                      "pretraining": training, "before": before, "retraining": variants, "mg": mg}))
-
-
-def retrain_selected(api, pre, op4, med4, iters, a, steps=200, every=25, npairs=2000, batch=16, lr=1e-4,
-                     seed=4001):
-    """The plain retraining (fixed set of eq. (4.3) pairs, Adam) with the
-    selection the pre-training uses: the weights are scored by the mean
-    CNN-FGMRES iteration count on 8 validation sources (row 24, not the
-    workload's row-4 sources) before training and every `every` steps, and the
-    best-scoring weights are kept.  Batches are random contiguous windows of
-    the pair set (the pairs are independent draws)."""
-    import torch
-    from paper_2405_17696_amd import synth
-    n = med4.kappa2.shape[0]
-    vb = torch.tensor(synth.point_sources(n, n, synth.surface_positions(n, 8), row=24, h=med4.h),
-                      dtype=torch.complex64, device="cuda")
-    net = api.cnn_load(pre)
     api.helm_autotune(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-
-    def score():
-        _, it, _, _, _ = api.helm_solve(op4, vb, tol=1e-6, precond="cnn_vu", maxit=a.maxit, net=net,
-                                        restart=a.restart)
-        return float(it.mean())
-
-    r, e = api.cnn_make_pairs(op4, 0, npairs, seed)
-    rng = np.random.default_rng(seed)
-    scores = [[0, score()]]
-    best = (scores[0][1], 0, api.cnn_get_params(net))
-    losses = []
-    for step in range(1, steps + 1):
-        s0 = int(rng.integers(0, npairs - batch + 1))
-        losses.append(api.cnn_loss_grad(net, op4, r[s0:s0 + batch], e[s0:s0 + batch]))
-        api.cnn_adam_step(net, lr)
-        if step % every == 0:
-            v = score()
-            scores.append([step, v])
-            if v < best[0]:
-                best = (v, step, api.cnn_get_params(net))
-    api.cnn_set_params(net, best[2])
-    torch.cuda.synchronize()
-    tr = time.perf_counter() - t0
+    for name, kw in (("alg2", dict(alg2=True, initial=128, data_epochs=3, epochs=4)),
+                     ("plain", dict(alg2=False, npairs=2000, steps=200))):
+        nn = api.cnn_load(pre)
+        hist, dsz, sec = training.retrain(nn, k2, g, med4.omega, med4.h, lr=1e-4, seed=4001, **kw)
+        variants[name] = {"retraining_seconds": sec, "steps": len(hist), "dataset": dsz,
+                          "loss_first": float(hist[0]), "loss_last20": float(np.mean(hist[-20:])),
+                          "after": iters(nn)}
+        print(f"c4 after {name}: {variants[name]['after']}", file=sys.stderr, flush=True)
+        nn.close()
     api.helm_autotune(1)
-    out = {"retraining_seconds": tr, "steps": steps, "dataset": npairs, "loss_first": float(losses[0]),
-           "loss_last20": float(np.mean(losses[-20:])), "validation_iters": scores, "selected_step": best[1]}
-    return out | {"after": iters("cnn_vu", med4, net)}
+    mg = training.solve_iterations(None, k2, g, med4.omega, med4.h, b, "mg", 20, a.maxit)
+    print(json.dumps({"workload": "c4 retraining in the paper's regime: network pre-trained on random linear media, "
+                                  "then retrained on the 5%-perturbed 256x256 layered medium (Alg. 2 and plain), "
+                                  "32 surface sources, CNN-FGMRES(10) vs MG-GMRES(20), tol 1e-6",
+                      "pretraining": info, "before": before, "retraining": variants, "mg": mg}))
 
 
 def main_c5(a):
+    """FWI on the 512x512 setting (128 sources, 128 receivers, 4 frequencies):
+    the misfit gradient over all sources with MG-GMRES(20) and with CNN-FGMRES(10)
+    (network pre-trained on random linear media, then retrained with Alg. 2 on
+    the initial model at its highest frequency, 512x512 = 10 points per
+    wavelength); the same with 16 simultaneous sources; the Gauss-Newton
+    Hessian-vector product and CG with the sensitivities at 1e-4; and Alg. 1
+    end to end on 16 of the sources with the diffusion regulariser and the
+    network retrained after every window."""
     import torch
-    from paper_2405_17696_amd import api, synth
+    from paper_2405_17696_amd import api, inversion, synth, training
     nsrc = a.sources or 128
     d = synth.config5_media(nsrc=nsrc)
-    t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    t = lambda v: torch.tensor(np.asarray(v, np.float32), device="cuda")
+    log = lambda m: print(m, file=sys.stderr, flush=True)
     gam = t(d["gamma"])
     nf = len(d["omegas"])
     n = d["kappa2_true"].size
+    h = d["h"]
     # observed data: library solves in the true model at tol 1e-8
-    ops_t = [api.helm_setup(t(d["kappa2_true"]), gam, w, d["h"]) for w in d["omegas"]]
+    ops_t = [api.helm_setup(t(d["kappa2_true"]), gam, w, h) for w in d["omegas"]]
     g = torch.zeros((nf * nsrc, n), dtype=torch.complex64, device="cuda")
     for f in range(nf):
-        for s, k in enumerate(d["src_idx"]):
-            g[f * nsrc + s, int(k)] = 1.0 / (d["h"] * d["h"])
+        for s_, k in enumerate(d["src_idx"]):
+            g[f * nsrc + s_, int(k)] = 1.0 / (h * h)
     rhs_op = [f for f in range(nf) for _ in range(nsrc)]
     u, _, _, _, _ = api.helm_solve(ops_t, g.reshape(-1), tol=1e-8, rhs_op=rhs_op, precond="mg", maxit=20000)
     rec = torch.as_tensor(np.asarray(d["rec_idx"]), device="cuda")
     dobs = u.reshape(nf, nsrc, n)[:, :, rec].to(torch.complex64).contiguous()
     for o in ops_t:
         o.close()
-    print("c5 data generated", file=sys.stderr, flush=True)
-    ops = [api.helm_setup(t(d["kappa2_init"]), gam, w, d["h"]) for w in d["omegas"]]
-    out = {}
-    for use_graph in (False, True):
+    del u, g
+    log("c5 data generated")
+    k0 = t(d["kappa2_init"])
+    # the network: pre-trained, then retrained (Alg. 2) on the initial model at
+    # the highest frequency (10 points per wavelength on this grid)
+    net, pre_info = pretrained_net(api, a)
+    api.helm_autotune(0)
+    hist, dsz, sec = training.retrain(net, k0, gam, d["omegas"][-1], h, alg2=True, initial=128, data_epochs=3,
+                                      epochs=4, lr=1e-4, seed=5001)
+    api.helm_autotune(1)
+    retrain_info = {"seconds": sec, "steps": len(hist), "dataset": dsz}
+    log(f"c5 network retrained on the initial model in {sec:.1f} s")
+    kws = {"mg": dict(precond="mg", maxit=a.maxit, restart=20),
+           "cnn_vu": dict(precond="cnn_vu", maxit=a.maxit, restart=a.restart, net=net)}
+    ops = [api.helm_setup(k0, gam, w, h) for w in d["omegas"]]
+    out = {"pretraining": pre_info, "retraining_on_initial_model": retrain_info}
+    grads = {}
+    for pc, kw in kws.items():
+        api.fwi_misfit_grad(ops, d["src_idx"][:1], d["rec_idx"], dobs[:, :1].contiguous(), tol=1e-6, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, grad, its, code = api.fwi_misfit_grad(ops, d["src_idx"], d["rec_idx"], dobs, tol=1e-6,
-                                                   precond="mg", maxit=a.maxit, restart=20, use_graph=use_graph)
+        phi, grad, its, code = api.fwi_misfit_grad(ops, d["src_idx"], d["rec_idx"], dobs, tol=1e-6, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        out["graph" if use_graph else "eager"] = {
-            "seconds": dt, "misfit": phi, "code": code, "solves": 2 * nf * nsrc,
-            "solves_per_s": 2 * nf * nsrc / dt, "forward_iters_mean": float(its[0].mean()),
-            "adjoint_iters_mean": float(its[1].mean()), "grad_norm": float(grad.double().norm())}
-        print(f"c5 {'graph' if use_graph else 'eager'} done in {dt:.1f} s", file=sys.stderr, flush=True)
+        grads[pc] = grad.double().clone()
+        out[f"gradient_{pc}"] = {"seconds": dt, "misfit": phi, "code": code, "solves": 2 * nf * nsrc,
+                                 "solves_per_s": 2 * nf * nsrc / dt, "forward_iters_mean": float(its[0].mean()),
+                                 "adjoint_iters_mean": float(its[1].mean()),
+                                 "forward_iters_per_frequency": [float(its[0][f].mean()) for f in range(nf)]}
+        log(f"c5 gradient {pc} in {dt:.1f} s")
+    full = grads["mg"]
+    out["gradient_cnn_vs_mg_relerr"] = float((grads["cnn_vu"] - full).norm() / full.norm())
+    out["speedup_cnn_vs_mg"] = out["gradient_mg"]["seconds"] / out["gradient_cnn_vu"]["seconds"]
     # simultaneous sources (Sec. 3.2): p Rademacher-encoded sources per frequency
-    full = grad.double().clone()
     p = a.encode_p
     X = synth.rademacher(nsrc, p, synth.rng_for(5, 2))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    phx, gx, itx, codex = api.fwi_misfit_grad_encoded(ops, d["src_idx"], X, d["rec_idx"], dobs, tol=1e-6,
-                                                      precond="mg", maxit=a.maxit, restart=20)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    gx = gx.double()
-    out[f"encoded_p{p}"] = {
-        "seconds": dt, "misfit_estimate": phx, "misfit_estimate_over_misfit": phx / phi, "code": codex,
-        "solves": 2 * nf * p, "solves_per_s": 2 * nf * p / dt, "forward_iters_mean": float(itx[0].mean()),
-        "adjoint_iters_mean": float(itx[1].mean()),
-        "grad_cosine_vs_all_sources": float((gx * full).sum() / (gx.norm() * full.norm()))}
-    print(f"c5 encoded p={p} done in {dt:.1f} s", file=sys.stderr, flush=True)
-    # Gauss-Newton Hessian-vector product (eq. 3.9-3.11) on every 8th source:
-    # forward, Born and adjoint solve batches
+    for pc, kw in kws.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phx, gx, itx, codex = api.fwi_misfit_grad_encoded(ops, d["src_idx"], X, d["rec_idx"], dobs, tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gx = gx.double()
+        out[f"encoded_p{p}_{pc}"] = {
+            "seconds": dt, "misfit_estimate_over_misfit": phx / out["gradient_mg"]["misfit"], "code": codex,
+            "solves": 2 * nf * p, "solves_per_s": 2 * nf * p / dt, "forward_iters_mean": float(itx[0].mean()),
+            "adjoint_iters_mean": float(itx[1].mean()),
+            "grad_cosine_vs_all_sources": float((gx * full).sum() / (gx.norm() * full.norm()))}
+        log(f"c5 encoded p={p} {pc} in {dt:.1f} s")
+    # Gauss-Newton products on every 8th source, then 3 CG steps with the
+    # sensitivities at 1e-4 (Sec. 5.4)
     src8 = np.asarray(d["src_idx"])[::8]
     dm = (full / full.abs().max()).float()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hv, ith, codeh = api.fwi_gn_hessvec(ops, src8, d["rec_idx"], dm, tol=1e-6, precond="mg", maxit=a.maxit,
-                                        restart=20)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["gn_hessvec"] = {"seconds": dt, "sources": len(src8), "code": codeh, "solves": 3 * nf * len(src8),
-                         "solves_per_s": 3 * nf * len(src8) / dt,
-                         "iters_mean_forward_born_adjoint": [float(ith[k].mean()) for k in range(3)],
-                         "curvature_dm_H_dm": float((hv.double() * dm.double()).sum())}
-    print(f"c5 Gauss-Newton product done in {dt:.1f} s", file=sys.stderr, flush=True)
-    # three CG steps of the damped Gauss-Newton system for the step -grad on the same sources
-    steps = 3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    damp = 1e-3 * out["gn_hessvec"]["curvature_dm_H_dm"] / float((dm.double() ** 2).sum())
-    xs, norms, _, codec = api.fwi_gn_cg(ops, src8, d["rec_idx"], (-full).float(), damping=damp, cg_iters=steps,
-                                        tol=1e-6, tol_sens=1e-4, precond="mg", maxit=a.maxit, restart=20)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["gn_cg"] = {"seconds": dt, "sources": len(src8), "steps": steps, "code": codec, "damping": damp,
-                    "solves": nf * len(src8) * (1 + 2 * steps), "residual_norms": norms.tolist(),
-                    "step_dot_grad": float((xs.double() * full).sum())}
-    print(f"c5 Gauss-Newton CG done in {dt:.1f} s", file=sys.stderr, flush=True)
-    # end to end: Alg. 1 over the four frequencies (window 1, one Gauss-Newton step
-    # of 3 CG steps per window) on the same 16 sources, from the initial model
-    from paper_2405_17696_amd import inversion
+    hv, ith, codeh = api.fwi_gn_hessvec(ops, src8, d["rec_idx"], dm, tol=1e-6, **kws["mg"])
+    curv = float((hv.double() * dm.double()).sum())
+    damp = 1e-3 * curv / float((dm.double() ** 2).sum())
+    for pc, kw in kws.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, norms, itc, codec = api.fwi_gn_cg(ops, src8, d["rec_idx"], (-full).float(), damping=damp, cg_iters=3,
+                                              tol=1e-6, tol_sens=1e-4, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"gn_cg_{pc}"] = {"seconds": dt, "sources": len(src8), "steps": 3, "code": codec, "damping": damp,
+                              "solves": nf * len(src8) * 7, "residual_norms": norms.tolist(),
+                              "born_adjoint_iters_mean": float(itc.mean()),
+                              "step_dot_grad": float((xs.double() * full).sum())}
+        log(f"c5 Gauss-Newton CG {pc} in {dt:.1f} s")
     for o in ops:
         o.close()
-    k0 = t(d["kappa2_init"])
+    # Alg. 1 end to end on 16 of the sources: one Gauss-Newton step (3 CG steps)
+    # per window, diffusion regulariser around the initial model, the network
+    # retrained (Alg. 2) after every window on the window's 10-ppw grid
     kt = t(d["kappa2_true"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    m, hist = inversion.frequency_continuation(k0, gam, list(d["omegas"]), d["h"], src8, d["rec_idx"],
-                                               dobs[:, ::8].contiguous(), cycles=[(0, nf - 1)], window=1, gn_iters=1,
-                                               damping=out["gn_cg"]["damping"], cg_iters=3, mu=1.0, tol=1e-6,
-                                               precond="mg", maxit=a.maxit, restart=20)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     err0 = float((k0 - kt).double().norm())
+    alpha = 1e-3 * damp
+    d8 = dobs[:, ::8].contiguous()
 
     def misfit_all(model):
-        ops_m = [api.helm_setup(model, gam, w, d["h"]) for w in d["omegas"]]
-        ph, _, _, _ = api.fwi_misfit_grad(ops_m, src8, d["rec_idx"], dobs[:, ::8].contiguous(), tol=1e-6,
-                                          precond="mg", maxit=a.maxit, restart=20)
+        ops_m = [api.helm_setup(model, gam, w, h) for w in d["omegas"]]
+        ph, _, _, _ = api.fwi_misfit_grad(ops_m, src8, d["rec_idx"], d8, tol=1e-6, **kws["mg"])
         for o in ops_m:
             o.close()
         return ph
-    out["frequency_continuation"] = {
-        "seconds": dt, "sources": len(src8), "windows": [list(st["window"]) for st in hist],
-        "misfit_before_each_step": [st["misfit"] for st in hist],
-        "solver_iterations_per_step": [int(st["iters"].sum()) for st in hist],
-        "model_error_over_initial": float((m - kt).double().norm()) / err0,
-        "misfit_all_frequencies_initial": misfit_all(k0), "misfit_all_frequencies_final": misfit_all(m)}
-    print(f"c5 frequency continuation done in {dt:.1f} s", file=sys.stderr, flush=True)
-    print(json.dumps({"workload": f"c5 FWI gradient: 512x512, {nsrc} sources, 128 receivers, {nf} frequencies, "
-                                  f"MG-GMRES(20) forward + adjoint, tol 1e-6; and with {p} simultaneous sources; "
-                                  "Gauss-Newton Hessian-vector product, 3 CG steps and frequency continuation on 16 of the sources",
+
+    for pc, kw in kws.items():
+        retrained = []
+
+        def retrain(m, i):
+            tt = time.perf_counter()
+            _, _, grid = inversion.retrain_on_window(net, m, gam, d["omegas"][i], h, seed=6000 + i)
+            retrained.append({"window_end": i, "grid": list(grid[:2]), "seconds": time.perf_counter() - tt})
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m, hist = inversion.frequency_continuation(k0, gam, list(d["omegas"]), h, src8, d["rec_idx"], d8,
+                                                   cycles=[(0, nf - 1)], window=1, gn_iters=1, damping=damp,
+                                                   cg_iters=3, mu=1.0, tol=1e-6, tol_sens=1e-4, reg="diff",
+                                                   alpha=alpha, allow_not_converged=True,
+                                                   retrain=retrain if pc != "mg" else None, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"frequency_continuation_{pc}"] = {
+            "seconds": dt, "sources": len(src8), "windows": [list(st["window"]) for st in hist],
+            "misfit_before_each_step": [st["misfit"] for st in hist],
+            "regulariser_before_each_step": [st["reg"] for st in hist],
+            "solver_iterations_per_window": [int(st["iters"].sum()) for st in hist],
+            "codes": [st["code"] for st in hist], "retraining": retrained,
+            "model_error_over_initial": float((m - kt).double().norm()) / err0,
+            "misfit_all_frequencies_initial": misfit_all(k0), "misfit_all_frequencies_final": misfit_all(m)}
+        log(f"c5 frequency continuation {pc} in {dt:.1f} s")
+    print(json.dumps({"workload": f"c5 FWI: 512x512, {nsrc} sources, 128 receivers, {nf} frequencies; misfit gradient "
+                                  "with MG-GMRES(20) and with CNN-FGMRES(10) (pre-trained network retrained on the "
+                                  f"initial model), tol 1e-6; {p} simultaneous sources; Gauss-Newton CG with "
+                                  "sensitivities at 1e-4; Alg. 1 with the diffusion regulariser and retraining after "
+                                  "every window on 16 of the sources",
                       "results": out}))
 
 
@@ -650,7 +695,7 @@ def main():
     if a.tune_file and os.path.exists(a.tune_file):
         from paper_2405_17696_amd import api
         api.helm_autotune_file(a.tune_file, save=False)
-    {"c2": main_c2, "c3": main_c3, "c4": main_c4, "c5": main_c5}[a.workload](a)
+    {"c2": main_c2, "c3": main_c3, "c4": main_c4, "c5": main_c5, "pretrain": main_pretrain}[a.workload](a)
     if a.tune_file:
         from paper_2405_17696_amd import api
         api.helm_autotune_file(a.tune_file, save=True)

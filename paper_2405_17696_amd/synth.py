@@ -132,12 +132,16 @@ def faulted_model(rng: np.random.Generator) -> FaultedModel:
 
 
 def velocity_linear(nz: int, nx: int, rng: np.random.Generator) -> np.ndarray:
-    """Random linear-in-depth model: random top and bottom values, uniform
-    increments in between (the pre-training media of Sec. 4.1)."""
+    """Random linear slowness-squared model (the pre-training media of Sec. 4.1):
+    velocities for the top and the bottom row drawn at random within the
+    physical range (top 1.5-2.5 km/s, bottom up to 4.5 km/s, faster than the
+    top), and m = 1/c^2 in uniform steps between the two rows' values;
+    returned as the velocity 1/sqrt(m)."""
     top = rng.uniform(1.5, 2.5)
     bot = rng.uniform(max(top, 2.5), 4.5)
     z = np.arange(nz)[:, None] / max(nz - 1, 1)
-    return np.repeat(top + (bot - top) * z, nx, axis=1)
+    m = 1.0 / top ** 2 + (1.0 / bot ** 2 - 1.0 / top ** 2) * z
+    return np.repeat(1.0 / np.sqrt(m), nx, axis=1)
 
 
 def kappa2_from_velocity(c: np.ndarray) -> np.ndarray:
