@@ -85,8 +85,12 @@ def parse():
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
-    ap.add_argument("--pretrain-steps", type=int, default=6000,
+    ap.add_argument("--pretrain-steps", type=int, default=16000,
                     help="pretrain / c3 / c4: Adam steps of the pre-training on random linear media (no --net)")
+    ap.add_argument("--pretrain-grids", default="128x128,128x256,256x256", help="pre-training grids, nz x nx")
+    ap.add_argument("--pretrain-ppw", default="5,12", help="pre-training points per wavelength: lo,hi (uniform)")
+    ap.add_argument("--pretrain-steps-per-medium", type=int, default=500, help="pre-training steps per random medium")
+    ap.add_argument("--pretrain-pairs", type=int, default=4096, help="fresh eq. (4.3) pairs per random medium")
     ap.add_argument("--c3-precond", default="cnn_vu", choices=["mg", "cnn_vu"], help="c3: preconditioner")
     ap.add_argument("--tune-file", default=None,
                     help="load convolution kernel choices from this file if it exists, save them after the run")
@@ -404,7 +408,9 @@ def main_c2(a):
     print(json.dumps(out))
 
 
-PRETRAIN_HALVINGS = (0.5, 0.75)   # fractions of the pre-training at which the learning rate halves
+# learning-rate halvings of the pre-training, as fractions of its steps (those
+# of the workload training: 1000, 3000, 8000 and 12000 of 16000 steps)
+PRETRAIN_HALVINGS = (1 / 16, 3 / 16, 8 / 16, 12 / 16)
 
 
 def pretrained_net(api, a, log=True):
@@ -418,7 +424,11 @@ def pretrained_net(api, a, log=True):
     net = api.cnn_create(seed=1)
     api.helm_autotune(0)
     k = a.pretrain_steps
-    info = training.pretrain(net, k, lr0=1e-3, halvings=tuple(int(f * k) for f in PRETRAIN_HALVINGS), seed=11,
+    grids = tuple(tuple(int(v) for v in g.split("x")) for g in a.pretrain_grids.split(","))
+    ppw = tuple(float(v) for v in a.pretrain_ppw.split(","))
+    info = training.pretrain(net, k, grids=grids, ppw_range=ppw, lr0=1e-3, pairs_per_medium=a.pretrain_pairs,
+                             steps_per_medium=a.pretrain_steps_per_medium,
+                             halvings=tuple(int(f * k) for f in PRETRAIN_HALVINGS), seed=11,
                              log=(lambda m: print(m, file=sys.stderr, flush=True)) if log else None)
     api.helm_autotune(1)
     if a.save_net:
@@ -502,8 +512,8 @@ def main_c4(a):
     """The paper's regime (Sec. 4.1-4.2, Alg. 2): a network pre-trained on random
     linear media meets the 5%-perturbed layered medium; iteration counts on the
     workload's 32 surface sources before retraining, after Alg. 2 retraining
-    (128 eq. (4.3) pairs doubled over 3 data epochs to 1024, 4 passes, Adam lr
-    1e-4, batch 16) and after plain retraining (2000 pairs, 200 steps, lr
+    (128 eq. (4.3) pairs doubled over 3 data epochs to 1024, 30 epochs, Adam lr
+    1e-4, batch 16: 1784 steps) and after plain retraining (2000 pairs, 200 steps, lr
     1e-4), each from the pre-trained weights, and MG-GMRES(20)."""
     import torch
     from paper_2405_17696_amd import api, synth, training
@@ -520,7 +530,7 @@ def main_c4(a):
     print(f"c4 before retraining: {before}", file=sys.stderr, flush=True)
     variants = {}
     api.helm_autotune(0)
-    for name, kw in (("alg2", dict(alg2=True, initial=128, data_epochs=3, epochs=4)),
+    for name, kw in (("alg2", dict(alg2=True, initial=128, data_epochs=3, epochs=30)),
                      ("plain", dict(alg2=False, npairs=2000, steps=200))):
         nn = api.cnn_load(pre)
         hist, dsz, sec = training.retrain(nn, k2, g, med4.omega, med4.h, lr=1e-4, seed=4001, **kw)

@@ -831,245 +831,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 1 ? 
     if (wc && tid == 0) work_atomic(wc, work);
 }
 
-// ------------------------------------------------------------------ tall tiles: 8 output rows per wave
-// 3x3 stride-1 forward convolution, 64 output channels per block, on 32 x 16
-// pixel tiles: wave w owns output rows 8w .. 8w+7 (128 pixels x 64 channels,
-// 32 accumulator tiles), one wave per SIMD.  For a fixed kx the wave holds the
-// three kernel rows' weight fragments (12) and walks the ten patch rows
-// 8w .. 8w+9 once, each pixel fragment feeding up to three (row, ky)
-// products: per 32-channel chunk 36 weight and 30 pixel fragments are read
-// from LDS for 288 MFMAs, against 72 fragments for 144 MFMAs with four rows per
-// wave (the LDS operand feed, not the matrix cores, bounds the 16 x 16 tiles).
-constexpr int TT_Y = 32;            // tile rows
-constexpr int TP_Y = TT_Y + 2;      // patch rows
-
-struct TallStage {
-    static constexpr int BN = 64;
-    static constexpr int PSEG = TP_Y * HP * (HC / 8);   // 16-byte segments of the patch
-    static constexpr int WSEG = 9 * BN * (HC / 8);      // and of the weights
-    static constexpr int PPT = (PSEG + 255) / 256, WPT = (WSEG + 255) / 256;
-    bf16x8 rp[PPT], rw[WPT];
-    unsigned po[PPT], wo[WPT];
-    __amdgpu_buffer_rsrc_t rs_p, rs_w;
-    int half = -1;
-
-    __device__ __forceinline__ void tile(const GemmArgs& a, int tid, int b, int ty0, int tx0, int s2) {
-        const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
-        const int cs = s2 ? a.c2 : a.c1;
-        const unsigned nrec = (unsigned)a.Hi * (unsigned)a.Wi * (unsigned)cs * 2u;
-        rs_p = brsrc(src, nrec);
-        half = s2;
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const int sg = tid + q * 256;
-            const int pix = sg >> 2, sub = sg & 3;
-            const int py = pix / HP, px = pix - py * HP;
-            const int yi = ty0 + py - 1, xi = tx0 + px - 1;
-            const bool in = sg < PSEG && (unsigned)yi < (unsigned)a.Hi && (unsigned)xi < (unsigned)a.Wi;
-            po[q] = in ? ((unsigned)(yi * a.Wi + xi) * (unsigned)cs + (unsigned)(sub * 8)) * 2u : nrec;
-        }
-    }
-    __device__ __forceinline__ void wset(const GemmArgs& a, int tid, int n0) {
-        const unsigned nrec = (unsigned)a.N * (unsigned)a.K * 2u;
-        rs_w = brsrc(a.w, nrec);
-        const int C = a.c1 + a.c2;
-#pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int sg = tid + q * 256;
-            const int row = sg >> 2, sub = sg & 3;   // row = tap * BN + n
-            const int tap = row / BN, n = row - tap * BN;
-            wo[q] = sg < WSEG && n0 + n < a.N ? (unsigned)((n0 + n) * a.K + tap * C + sub * 8) * 2u : nrec;
-        }
-    }
-    __device__ __forceinline__ void issue(const GemmArgs& a, int tid, int c0) {
-        const unsigned cc = (unsigned)(half ? c0 - a.c1 : c0) * 2u;
-#pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            if (tid + q * 256 < PSEG) rp[q] = bload8(rs_p, po[q] + cc);
-#pragma unroll
-        for (int q = 0; q < WPT; ++q)
-            if (tid + q * 256 < WSEG) rw[q] = bload8(rs_w, wo[q] + (unsigned)c0 * 2u);
-    }
-    __device__ __forceinline__ void store(bf16 (*Ps)[HLD], bf16 (*Ws)[BN][HLD], int tid) const {
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const int sg = tid + q * 256;
-            if (sg >= PSEG) break;
-            *reinterpret_cast<bf16x8*>(&Ps[sg >> 2][(sg & 3) * 8]) = rp[q];
-        }
-#pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int sg = tid + q * 256;
-            if (sg >= WSEG) break;
-            const int row = sg >> 2;
-            *reinterpret_cast<bf16x8*>(&Ws[row / BN][row % BN][(sg & 3) * 8]) = rw[q];
-        }
-    }
-};
-
-__device__ __forceinline__ void tall_mma(const bf16 (*Ps)[HLD], const bf16 (*Ws)[64][HLD], f32x4 (&acc)[8][4],
-                                         int lane, int wave) {
-#pragma unroll
-    for (int kx = 0; kx < 3; ++kx) {
-        bf16x8 fw[3][4];
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                fw[ky][j] = *reinterpret_cast<const bf16x8*>(&Ws[3 * ky + kx][j * 16 + (lane & 15)][(lane >> 4) * 8]);
-#pragma unroll
-        for (int r = 0; r < 10; ++r) {
-            const bf16x8 fx =
-                *reinterpret_cast<const bf16x8*>(&Ps[(wave * 8 + r) * HP + (lane & 15) + kx][(lane >> 4) * 8]);
-#pragma unroll
-            for (int ky = 0; ky < 3; ++ky) {
-                const int i = r - ky;              // output row 8w + i reads patch row 8w + i + ky
-                if (i < 0 || i > 7) continue;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[ky][j], fx, acc[i][j], 0, 0, 0);
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k_conv3_tall(GemmArgs a,
-                                                                                           unsigned long long* wc) {
-    constexpr int BN = 64;
-    __shared__ __attribute__((aligned(16))) bf16 Ps[TP_Y * HP][HLD];
-    __shared__ __attribute__((aligned(16))) bf16 Ws[9][BN][HLD];
-    __shared__ __attribute__((aligned(16))) float bias_s[BN];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tiles_x = (a.Wo + HT - 1) / HT, tiles_y = (a.Ho + TT_Y - 1) / TT_Y;
-    int t = blockIdx.x;
-    const int tx0 = (t % tiles_x) * HT;
-    t /= tiles_x;
-    const int ty0 = (t % tiles_y) * TT_Y;
-    const int b = t / tiles_y;
-    const int n0 = blockIdx.y * BN;
-    if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) return;
-    if (wc && tid == 0) {
-        const int my = a.Ho - ty0 < TT_Y ? a.Ho - ty0 : TT_Y, mx = a.Wo - tx0 < HT ? a.Wo - tx0 : HT;
-        const int nr = a.N - n0 < BN ? a.N - n0 : BN;
-        work_atomic(wc, 2ull * my * mx * nr * (unsigned long long)(9 * (a.c1 + a.c2)));
-    }
-    if (tid < BN) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[n0 + tid] : 0.f;
-    f32x4 acc[8][4];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    TallStage st;
-    const int nchunk = (a.c1 + a.c2) / HC;
-    st.tile(a, tid, b, ty0, tx0, 0);
-    st.wset(a, tid, n0);
-    st.issue(a, tid, 0);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        st.store(Ps, Ws, tid);
-        __syncthreads();
-        if (ch + 1 < nchunk) {
-            const int c0 = (ch + 1) * HC;
-            if (c0 == a.c1) st.tile(a, tid, b, ty0, tx0, 1);
-            st.issue(a, tid, c0);
-        }
-        tall_mma(Ps, Ws, acc, lane, wave);
-        __syncthreads();
-    }
-    const int x = tx0 + (lane & 15);
-    if (a.outf) {
-        // FP32 copy requested (single-layer hooks): finish in registers, as the
-        // 16 x 16 kernels' direct epilogue does (residual added before rounding)
-        if (x >= a.Wo) return;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int y = ty0 + wave * 8 + i;
-            if (y >= a.Ho) continue;
-            const long m = ((long)b * a.Ho + y) * a.Wo + x;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int nl = j * 16 + (lane >> 4) * 4, n = n0 + nl;
-                if (n >= a.N) continue;
-                f32x4 v = acc[i][j];
-                const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
-                                         : *reinterpret_cast<const float4*>(bias_s + nl);
-                v[0] += bb.x;
-                v[1] += bb.y;
-                v[2] += bb.z;
-                v[3] += bb.w;
-                if (a.resid) {
-                    const bf16x4 r = *reinterpret_cast<const bf16x4*>(a.resid + m * a.N + n);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
-                }
-                if (a.relu)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
-                if (a.out) {
-                    bf16x4 o;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
-                    *reinterpret_cast<bf16x4*>(a.out + m * a.N + n) = o;
-                }
-                *reinterpret_cast<f32x4*>(a.outf + m * a.N + n) = v;
-            }
-        }
-        return;
-    }
-    // epilogue through LDS: bias (or bias map), ReLU, bf16; then whole 16-byte
-    // rows per lane, with the residual added on them
-    constexpr int SP = BN + 8;
-    bf16* scratch = &Ps[0][0];
-    static_assert(sizeof(Ps) + sizeof(Ws) >= (size_t)TT_Y * HT * SP * sizeof(bf16), "epilogue scratch");
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int y = ty0 + wave * 8 + i;
-        const bool in = x < a.Wo && y < a.Ho;
-        const int p = (wave * 8 + i) * HT + (lane & 15);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int nl = j * 16 + (lane >> 4) * 4, n = n0 + nl;
-            f32x4 v = acc[i][j];
-            if (in && n < a.N) {
-                const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
-                                         : *reinterpret_cast<const float4*>(bias_s + nl);
-                v[0] += bb.x;
-                v[1] += bb.y;
-                v[2] += bb.z;
-                v[3] += bb.w;
-                if (a.relu && !a.resid)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
-            }
-            bf16x4 o;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
-            *reinterpret_cast<bf16x4*>(scratch + p * SP + nl) = o;
-        }
-    }
-    __syncthreads();
-    constexpr int CPP = BN / 8;
-#pragma unroll 4
-    for (int r = 0; r < TT_Y * HT * CPP / 256; ++r) {
-        const int k = tid + r * 256;
-        const int p = k / CPP, c = k - p * CPP;
-        const int y = ty0 + p / HT, xx = tx0 + (p & (HT - 1)), n = n0 + c * 8;
-        if (y < a.Ho && xx < a.Wo && n < a.N) {
-            const long o = (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n;
-            bf16x8 tv = *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
-            if (a.resid) {
-                const bf16x8 rr = *reinterpret_cast<const bf16x8*>(a.resid + o);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    float w = (float)tv[e] + (float)rr[e];
-                    if (a.relu) w = w > 0.f ? w : 0.f;
-                    tv[e] = (bf16)w;
-                }
-            }
-            *reinterpret_cast<bf16x8*>(a.out + o) = tv;
-        }
-    }
-}
-
 // ------------------------------------------------------------------ first layer (few input channels)
 // 3x3 stride-1 convolution with C <= 4 input channels and N <= 64 outputs (the
 // networks' first layers, C = 2): FP32 FMAs with the weights in LDS.  Thread t
@@ -1618,7 +1379,7 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // tuned (accumulating ones would add each candidate's result).
 enum ConvKernel {
     CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W,
-    CK_PERS16, CK_TALL64, CK_COUNT
+    CK_PERS16, CK_COUNT
 };
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
@@ -1633,8 +1394,6 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_GEMM64W: return a.N >= 128;
         case CK_GEMM128W: return a.N >= 64;
         case CK_PERS16: return halo && a.N <= 16 && C == HC;   // narrow outputs (the 2-channel head)
-        case CK_TALL64:   // forward, at least 64 output channels
-            return halo && a.gmode == G_CONV && a.epi == E_FWD && a.N >= 64 && (a.out || a.outf) && (a.N & 7) == 0;
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1679,11 +1438,6 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
             else
                 launch_halo_ck<0, E_FWD>(a, s, wc, ck);
             break;
-        case CK_TALL64: {
-            const unsigned tiles = (unsigned)(((a.Ho + TT_Y - 1) / TT_Y) * ((a.Wo + HT - 1) / HT) * a.B);
-            TIMED_LAUNCH("k_conv", s, k_conv3_tall, dim3(tiles, (a.N + 63) / 64), dim3(256), 0, s, a, wc);
-            break;
-        }
         case CK_FIRST2: {
             const long nseg = (long)a.B * a.Ho * ((a.Wo + 15) / 16);
             const dim3 grid((unsigned)std::max<long>(1, std::min<long>(4096, (nseg + 3) / 4)));

@@ -49,7 +49,7 @@ def retrain_on_window(net, m: torch.Tensor, gamma: torch.Tensor, omega: float, h
     else:
         mt = api.helm_resample(m, nz_t, nx_t)
         gt = api.helm_resample(gamma, nz_t, nx_t)
-    kw = dict(npairs=128, batch=16, steps=0, lr=1e-4, alg2_initial=128, alg2_data_epochs=3, alg2_epochs=3)
+    kw = dict(npairs=128, batch=16, steps=10 ** 6, lr=1e-4, alg2_initial=128, alg2_data_epochs=3, alg2_epochs=30)
     kw.update(train_kw)
     op = api.helm_setup(mt, gt, omega, hx_t, hz=hz_t)
     try:

@@ -110,36 +110,3 @@ def test_precond_apply_full_width_full_size(gpu):
     for s in range(2):
         assert relerr(e[s], ref[s]) <= 2e-2
 
-
-CK_TALL64 = 10  # the 32 x 16-tile kernel (8 output rows per wave)
-
-
-@pytest.mark.parametrize("H,W_,c1,c2,bcast,cout,resid", [
-    (128, 128, 64, 0, False, 64, False),      # level-1 shape, 4 x 8 x B tiles
-    (64, 64, 128, 128, False, 128, False),    # level-2 merge: concatenated sources, two channel blocks
-    (37, 50, 64, 64, True, 64, False),        # ragged tiles, broadcast context
-    (32, 32, 256, 0, False, 256, True),       # level-3 residual layer, four channel blocks
-])
-def test_tall_tile_conv(gpu, H, W_, c1, c2, bcast, cout, resid):
-    Bn = 4
-    print("tall-tile conv", H, W_, c1, c2, cout, flush=True)
-    x1 = rnd((Bn, H, W_, c1), 61)
-    x2 = rnd(((1 if bcast else Bn), H, W_, c2), 62) if c2 else None
-    Wt = rnd((cout, 3, 3, c1 + c2), 63, scale=np.sqrt(2.0 / (9 * (c1 + c2))))
-    b = rnd((cout,), 64, 0.1)
-    r = rnd((Bn, H, W_, cout), 65) if resid else None
-    api.helm_conv_force(CK_TALL64)
-    try:
-        y = api.cnn_layer_forward(0, 1, x1, Wt, b, x2=x2, bcast2=bcast, resid=r, relu=True)
-    finally:
-        api.helm_conv_force(-1)
-    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])], axis=-1)
-    ref = U.conv3x3(x, Wt, b, 1)
-    if resid:
-        ref = ref + r
-    ref = np.maximum(ref, 0)
-    e = relerr(y, ref)
-    print("rel err", e)
-    assert e <= 1e-5                  # the layer hook returns the FP32 result (BF16 inputs, FP32 accumulation)
-    for s in range(Bn):
-        assert relerr(y[s], ref[s]) <= 1e-5
