@@ -139,7 +139,7 @@ __global__ void k_level_wdinv(const c128* __restrict__ sl, int nz, int nx, Sten<
 
 int setup_levels(helm_op* op, const float* k2, const float* g, hipStream_t s) {
     double w2 = op->omega * op->omega;
-    // the single-workgroup coarse polynomial needs 2 x 64 KiB of dynamic LDS
+    // the single-workgroup coarse polynomial needs 2 x 64 KiB of dynamic LDS (two residual buffers)
     static const bool lds_ok =
         hipFuncSetAttribute((const void*)k_poly_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             2 * POLY_LDS_MAX * (int)sizeof(c128)) == hipSuccess &&
@@ -407,8 +407,11 @@ __global__ __launch_bounds__(256) void k_poly_term(const cx<T>* __restrict__ src
 }
 
 // Whole coarsest-level polynomial in one workgroup per right-hand side, the
-// residual resident in LDS (FP64) and the iterate in registers.  Used when the
-// level has at most POLY_LDS_MAX nodes.
+// residual resident in LDS (FP64) and the iterate and the diagonal terms in
+// registers.  The residual is double buffered in LDS, so one barrier per
+// factor suffices: a thread overwrites buffer (t+1) % 2 only after the barrier
+// of factor t, which every thread reaches after its reads of factor t-1 from
+// that buffer.  Used when the level has at most POLY_LDS_MAX nodes.
 template <typename T>
 __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restrict__ src, cx<T>* __restrict__ out,
                                                            const c128* __restrict__ sl, int nz, int nx,
@@ -424,10 +427,8 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
     src += (long)rl * N;
     out += (long)rl * N;
     add_work(wc, (unsigned long long)N * 2 * sizeof(cx<T>));
-    extern __shared__ c128 lds_poly[];
-    c128* rs = lds_poly;       // residual, N entries
-    c128* ss_ = lds_poly + N;  // mass term minus the stencil diagonal, N entries
-    c128 xr[POLY_NPT], rr[POLY_NPT];
+    extern __shared__ c128 lds_poly[];   // two residual buffers of N entries
+    c128 xr[POLY_NPT], rr[POLY_NPT], sd[POLY_NPT];
     int ii[POLY_NPT], kk[POLY_NPT];
 #pragma unroll
     for (int q = 0; q < POLY_NPT; ++q) {
@@ -436,9 +437,11 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
         rr[q] = n < N ? ccast<double>(src[n]) : mk(0.0, 0.0);
         ii[q] = n / nx;
         kk[q] = n - ii[q] * nx;
+        sd[q] = mk(0.0, 0.0);
         if (n < N) {
+            // stencil diagonal minus the mass term
             NodeSten<double> ns = node_sten(sten, ii[q], kk[q], nz, nx);
-            ss_[n] = mk(ns.dg - sl[n].re, -sl[n].im);
+            sd[q] = mk(ns.dg - sl[n].re, -sl[n].im);
         }
     }
     for (int t = 0; t < deg; ++t) {
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
 #pragma unroll
         for (int q = 0; q < POLY_NPT; ++q) xr[q] = xr[q] + rr[q] * it;
         if (t == deg - 1) break;
-        __syncthreads();
+        c128* rs = lds_poly + (t & 1) * N;
 #pragma unroll
         for (int q = 0; q < POLY_NPT; ++q) {
             int n = threadIdx.x + q * POLY_THREADS;
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
             c128 nn = i > 0 ? rs[n - nx] : zero, sv = i + 1 < nz ? rs[n + nx] : zero;
             const bool lx = k == nx - 1, lz = i == nz - 1;
             double cw = lx ? sten.axl : sten.ax, cn = lz ? sten.azl : sten.az;
-            c128 pr = ss_[n] * rr[q] - cw * w - sten.ax * e - cn * nn - sten.az * sv;
+            c128 pr = sd[q] * rr[q] - cw * w - sten.ax * e - cn * nn - sten.az * sv;
             rr[q] = rr[q] - pr * it;
         }
     }

@@ -35,12 +35,14 @@ def training_grid(nz: int, nx: int, h: float, omega: float, c_min: float, ppw: f
 
 
 def retrain_on_window(net, m: torch.Tensor, gamma: torch.Tensor, omega: float, h: float, ppw: float = 10.0,
-                      seed: int = 0, **train_kw):
-    """Alg. 2 retraining of `net` on the medium m at frequency omega, on the
-    grid with `ppw` points per wavelength at omega (model and attenuation
-    resampled bilinearly by the library).  train_kw go to cnn_precond_train
-    (defaults: Alg. 2 from 128 pairs, 3 data epochs, lr 1e-4).  Returns
-    (loss history, dataset size, training grid)."""
+                      seed: int = 0, alg2: bool = True, **train_kw):
+    """Retraining of `net` on the medium m at frequency omega, on the grid with
+    `ppw` points per wavelength at omega (model and attenuation resampled
+    bilinearly by the library): Alg. 2 (the paper's defaults: 128 pairs, 3 data
+    epochs, 30 epochs, lr 1e-4) or, with alg2=False, plain retraining on 2000
+    fresh eq. (4.3) pairs for 200 steps at lr 1e-4.  train_kw override
+    cnn_precond_train's arguments.  Returns (loss history, dataset size,
+    training grid)."""
     nz, nx = m.shape
     c_min = 1.0 / math.sqrt(float(m.max()))
     nz_t, nx_t, hx_t, hz_t = training_grid(nz, nx, h, omega, c_min, ppw)
@@ -49,7 +51,10 @@ def retrain_on_window(net, m: torch.Tensor, gamma: torch.Tensor, omega: float, h
     else:
         mt = api.helm_resample(m, nz_t, nx_t)
         gt = api.helm_resample(gamma, nz_t, nx_t)
-    kw = dict(npairs=128, batch=16, steps=10 ** 6, lr=1e-4, alg2_initial=128, alg2_data_epochs=3, alg2_epochs=30)
+    if alg2:
+        kw = dict(npairs=128, batch=16, steps=10 ** 6, lr=1e-4, alg2_initial=128, alg2_data_epochs=3, alg2_epochs=30)
+    else:
+        kw = dict(npairs=2000, batch=16, steps=200, lr=1e-4)
     kw.update(train_kw)
     op = api.helm_setup(mt, gt, omega, hx_t, hz=hz_t)
     try:
@@ -63,14 +68,15 @@ def frequency_continuation(kappa2: torch.Tensor, gamma: torch.Tensor, omegas, h:
                            dobs: torch.Tensor, cycles, window: int, gn_iters: int, damping: float, cg_iters: int,
                            mu: float = 1.0, reg: str = "none", alpha: float = 0.0, m_ref: torch.Tensor | None = None,
                            tol: float = 1e-6, tol_sens: float = 0.0, retrain=None, allow_not_converged=False,
-                           **solve_kw):
+                           log=None, **solve_kw):
     """kappa2, gamma float32 [nz][nx] and dobs complex64 [nf][ns][nrec] on the
     GPU.  reg / alpha / m_ref: the regulariser ("high": eq. 5.1, "diff":
     eq. 5.2) around m_ref (default: the initial model, kept fixed).
     retrain: None, or a callable retrain(m, i) run after the window that ends
     at frequency index i (e.g. retrain_on_window with the solve's network).
     A step whose solves missed their tolerance raises unless
-    allow_not_converged; a non-finite solve always raises.  Returns the final
+    allow_not_converged; a non-finite solve always raises.  log: optional
+    callable given a one-line summary after every step.  Returns the final
     model and, per step, a dict: window (lo, hi), misfit (data misfit before
     the step), reg (R before the step), norms (CG residual norms), iters
     (solver iterations of every batch of the step, [2 + 2 cg_iters][nfreq][nsrc]),
@@ -98,6 +104,9 @@ def frequency_continuation(kappa2: torch.Tensor, gamma: torch.Tensor, omegas, h:
                 m, nxt = nxt, m
                 history.append({"window": (lo, i), "misfit": out["misfit"], "reg": out["reg"],
                                 "norms": out["norms"], "iters": out["iters"], "code": code})
+                if log:
+                    log(f"Gauss-Newton step on window {lo}..{i}: misfit {out['misfit']:.6g}, "
+                        f"{int(out['iters'].sum())} solver iterations, code {code}")
             if retrain is not None:
                 retrain(m, i)
     return m, history

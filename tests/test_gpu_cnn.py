@@ -346,3 +346,30 @@ def test_trained_network_beats_multigrid(gpu):
     print("iterations: untrained", it0.mean(), "trained", it1.mean(), "MG-GMRES(20)", itm.mean())
     assert c0 == 0 and cm == 0 and c1 == 0
     assert it1.mean() < itm.mean() and it1.mean() < it0.mean()
+
+
+def test_pretrain_then_retrain_lowers_iterations(gpu):
+    """The paper's regime at 64 x 64 (Sec. 4.1-4.2): a network pre-trained on
+    random linear slowness-squared media, then retrained on a layered medium
+    it has not seen, needs fewer CNN-FGMRES(10) iterations on that medium's
+    surface sources after the retraining than before it."""
+    from paper_2405_17696_amd import synth, training
+    n = 64
+    net = api.cnn_create(seed=1)
+    print("pre-training on linear media at 64x64", flush=True)
+    info = training.pretrain(net, 2000, grids=((n, n),), ppw_range=(10.0, 10.0), pairs_per_medium=1024,
+                             steps_per_medium=250, halvings=(125, 375, 1000, 1500), seed=21)
+    c = synth.velocity_layered(n, n, np.random.default_rng(62))
+    med = synth.medium_from_velocity(c)
+    k2 = torch.tensor(np.asarray(med.kappa2, np.float32), device="cuda")
+    g = torch.tensor(np.asarray(med.gamma, np.float32), device="cuda")
+    b = torch.tensor(synth.point_sources(n, n, synth.surface_positions(n, 8), h=med.h), dtype=torch.complex64,
+                     device="cuda")
+    before = training.solve_iterations(net, k2, g, med.omega, med.h, b)
+    hist, dsz, sec = training.retrain(net, k2, g, med.omega, med.h, alg2=False, npairs=1024, steps=200, lr=1e-4,
+                                      seed=22)
+    after = training.solve_iterations(net, k2, g, med.omega, med.h, b)
+    mg = training.solve_iterations(None, k2, g, med.omega, med.h, b, precond="mg", restart=20)
+    print("pre-training", info["seconds"], "s; iterations before", before, "after", after, "MG-GMRES(20)", mg)
+    assert before["converged"] == after["converged"] == 8
+    assert after["iters_mean"] < before["iters_mean"]
