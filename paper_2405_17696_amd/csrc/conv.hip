@@ -758,6 +758,253 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN <= 32 ? 
         halo_epilogue<BN, EPI>(a, acc, b, ty0, tx0, n0, lane, wave);
 }
 
+// ------------------------------------------------------------------ double-buffered wide-tile halo kernel
+// One 16 x 32 output tile and BN = 64 output channels per 512-thread block.
+// Each 32-channel chunk of the 18 x 34 input patch and the chunk's nine taps of
+// weights go straight from memory into LDS with 16-byte buffer loads (lane l of
+// a load instruction lands at byte 16 l of its 1 KB destination, so the dense
+// [pixel][32 channel] layout needs no register staging; out-of-image pixels and
+// weight rows past N are read past the end of their buffer and arrive as zeros).
+// Two LDS stages alternate: while the eight waves multiply chunk c out of one
+// stage, the loads of chunk c + 1 fill the other, so a chunk costs one barrier.
+// The 512-pixel tile halves the weight traffic per output of a 16 x 16 tile.
+// Wave w owns output rows 4 (w & 3) .. + 3 of column half w >> 2.
+constexpr int DTY = 16, DTX = 32;                 // output tile
+constexpr int DPY = DTY + 2, DPX = DTX + 2;       // input patch
+constexpr int DPSEG = DPY * DPX * 4;              // 16-byte segments of one patch chunk (2448)
+constexpr int DWSEG = 9 * 64 * 4;                 // and of one weight chunk (2304)
+constexpr int DPINS = (DPSEG + 63) / 64;          // wave-wide load instructions per patch chunk (39)
+constexpr int DWINS = DWSEG / 64;                 // per weight chunk (36)
+constexpr int DPPT = (DPINS + 7) / 8, DWPT = (DWINS + 7) / 8;   // per wave (5, 5)
+constexpr int DPBYTES = DPINS * 1024;             // patch region of a stage (the last load's
+                                                  // lanes past the patch write zeros into its tail)
+constexpr int DSTAGE = DPBYTES + DWINS * 1024;    // bytes per LDS stage (76800)
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+struct DlStage {
+    unsigned po[DPPT];   // per-lane byte offsets of this wave's patch segments (past the range: zeros)
+    unsigned wo[DWPT];   // and of its weight segments
+
+    // Patch offsets of the tile at (ty0, tx0) in input half s2 (0: a1, 1: a2).
+    __device__ __forceinline__ void tile(const GemmArgs& a, int lane, int wave, int ty0, int tx0, int s2) {
+        const int cs = s2 ? a.c2 : a.c1;
+        const unsigned nrec = (unsigned)a.Hi * (unsigned)a.Wi * (unsigned)cs * 2u;
+#pragma unroll
+        for (int q = 0; q < DPPT; ++q) {
+            const int sg = (wave + 8 * q) * 64 + lane;
+            const int pix = sg >> 2, sub = sg & 3;
+            const int py = pix / DPX, px = pix - py * DPX;
+            const int yi = ty0 + py - 1, xi = tx0 + px - 1;
+            const bool in = sg < DPSEG && (unsigned)yi < (unsigned)a.Hi && (unsigned)xi < (unsigned)a.Wi;
+            po[q] = in ? ((unsigned)(yi * a.Wi + xi) * (unsigned)cs + (unsigned)(sub * 8)) * 2u : nrec;
+        }
+    }
+    __device__ __forceinline__ void wset(const GemmArgs& a, int lane, int wave, int n0) {
+        const unsigned nrec = (unsigned)a.N * (unsigned)a.K * 2u;
+        const int C = a.c1 + a.c2;
+#pragma unroll
+        for (int q = 0; q < DWPT; ++q) {
+            const int sg = (wave + 8 * q) * 64 + lane;   // row = tap * 64 + n
+            const int row = sg >> 2, sub = sg & 3;
+            const int tap = row >> 6, n = row & 63;
+            wo[q] = sg < DWSEG && n0 + n < a.N ? (unsigned)((n0 + n) * a.K + tap * C + sub * 8) * 2u : nrec;
+        }
+    }
+    // Loads of sample b's chunk at absolute input channel c0 into the stage at st (bytes); the
+    // patch offsets must refer to the chunk's input half.
+    __device__ __forceinline__ void issue(const GemmArgs& a, int wave, int b, int c0, unsigned char* st) const {
+        const bool s2 = c0 >= a.c1;
+        const bf16* src = s2 ? a.a2 + b * a.abs2 : a.a1 + b * a.abs1;
+        const unsigned nrec = (unsigned)a.Hi * (unsigned)a.Wi * (unsigned)(s2 ? a.c2 : a.c1) * 2u;
+        const __amdgpu_buffer_rsrc_t rs_p = brsrc(src, nrec);
+        const __amdgpu_buffer_rsrc_t rs_w = brsrc(a.w, (unsigned)a.N * (unsigned)a.K * 2u);
+        const unsigned cc = (unsigned)(s2 ? c0 - a.c1 : c0) * 2u;
+#pragma unroll
+        for (int q = 0; q < DPPT; ++q) {
+            const int ins = wave + 8 * q;
+            if (ins < DPINS)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_p, (lds_void_t*)(st + ins * 1024), 16, po[q] + cc, 0, 0, 0);
+        }
+        unsigned char* ws = st + DPBYTES;
+#pragma unroll
+        for (int q = 0; q < DWPT; ++q) {
+            const int ins = wave + 8 * q;
+            if (ins < DWINS)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_w, (lds_void_t*)(ws + ins * 1024), 16, wo[q] + (unsigned)c0 * 2u,
+                                                         0, 0, 0);
+        }
+    }
+};
+
+// acc[i][j] += one staged chunk; P = [DPY*DPX][32], W = [9][64][32] (bf16).
+// Tap by tap, with the next tap's eight fragments (four weight rows, four patch
+// rows) read from LDS before the current tap's sixteen MFMAs are issued: a wave
+// hides its own LDS latency behind a whole tap.  The scheduling barriers keep
+// the compiler from sinking the reads next to their uses.
+__device__ __forceinline__ void dl_mma(const bf16* P, const bf16* W, f32x4 (&acc)[4][4], int lane, int rg, int cx) {
+    const int g8 = (lane >> 4) * 8;
+    const bf16* pw = W + (lane & 15) * 32 + g8;
+    const bf16* pp = P + ((rg * 4) * DPX + cx * 16 + (lane & 15)) * 32 + g8;
+    bf16x8 fw[2][4], fx[2][4];
+    auto fetch = [&](int tap, int buf) {
+        const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fw[buf][j] = *reinterpret_cast<const bf16x8*>(pw + (tap * 64 + j * 16) * 32);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fx[buf][i] = *reinterpret_cast<const bf16x8*>(pp + ((i + ky) * DPX + kx) * 32);
+    };
+    fetch(0, 0);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int cur = tap & 1;
+        if (tap + 1 < 9) fetch(tap + 1, cur ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[cur][j], fx[cur][i], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Epilogue of one 16 x 32 tile (E_FWD).  With bf16 output and N a multiple of 8
+// the accumulators go through the LDS scratch sc (>= 512 * 72 bf16, free when
+// called; every thread of the block must call this): bias or bias map, ReLU when
+// there is no residual, rounding to bf16, then whole 16-byte channel groups per
+// store with the residual added on them.  Otherwise a per-element register path.
+__device__ __forceinline__ void dl_epilogue(const GemmArgs& a, const f32x4 (&acc)[4][4], int b, int ty0, int tx0,
+                                            int n0, int tid, bf16* sc, const float* bias_s) {
+    const int lane = tid & 63, wave = tid >> 6, rg = wave & 3, cx = wave >> 2;
+    const int x = tx0 + cx * 16 + (lane & 15);
+    if ((a.N & 7) == 0 && a.out && !a.outf) {
+        constexpr int SP = 64 + 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = rg * 4 + i, y = ty0 + py;
+            const bool in = x < a.Wo && y < a.Ho;
+            const int p = py * DTX + cx * 16 + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int nl = j * 16 + (lane >> 4) * 4, n = n0 + nl;
+                f32x4 v = acc[i][j];
+                if (in && n < a.N) {
+                    const float4 bb = a.bmap ? bmap4(a.bmap + ((long)y * a.Wo + x) * a.N + n)
+                                             : *reinterpret_cast<const float4*>(bias_s + nl);
+                    v[0] += bb.x;
+                    v[1] += bb.y;
+                    v[2] += bb.z;
+                    v[3] += bb.w;
+                    if (a.relu && !a.resid)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                }
+                bf16x4 o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+                *reinterpret_cast<bf16x4*>(sc + p * SP + nl) = o;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < DTY * DTX * 8 / 512; ++r) {
+            const int k = tid + r * 512;
+            const int p = k >> 3, c = k & 7;
+            const int y = ty0 + p / DTX, xx = tx0 + p % DTX, n = n0 + c * 8;
+            if (y < a.Ho && xx < a.Wo && n < a.N) {
+                const long o = (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n;
+                bf16x8 v = *reinterpret_cast<const bf16x8*>(sc + p * SP + c * 8);
+                if (a.resid) {
+                    const bf16x8 rr = *reinterpret_cast<const bf16x8*>(a.resid + o);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        float w = (float)v[e] + (float)rr[e];
+                        if (a.relu) w = w > 0.f ? w : 0.f;
+                        v[e] = (bf16)w;
+                    }
+                }
+                *reinterpret_cast<bf16x8*>(a.out + o) = v;
+            }
+        }
+        return;
+    }
+    if (x >= a.Wo) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ty0 + rg * 4 + i;
+        if (y >= a.Ho) continue;
+        const long m = ((long)b * a.Ho + y) * a.Wo + x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + j * 16 + (lane >> 4) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ne = n + e;
+                if (ne >= a.N) break;
+                float v = acc[i][j][e];
+                v += a.bmap ? (float)a.bmap[((long)y * a.Wo + x) * a.N + ne] : (a.bias ? a.bias[ne] : 0.f);
+                if (a.resid) v += (float)a.resid[m * a.N + ne];
+                if (a.relu) v = v > 0.f ? v : 0.f;
+                if (a.out) a.out[m * a.N + ne] = (bf16)v;
+                if (a.outf) a.outf[m * a.N + ne] = v;
+            }
+        }
+    }
+}
+
+// Forward convolutions only (E_FWD); one 16 x 32 tile per block.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_dl(GemmArgs a,
+                                                                                         unsigned long long* wc) {
+    // two separate arrays (not one [2][...] array), so that the compiler can tell the loads
+    // into one stage from the reads of the other and does not wait for them before reading
+    __shared__ __attribute__((aligned(1024))) unsigned char stage0[DSTAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage1[DSTAGE];
+    __shared__ __attribute__((aligned(16))) float bias_s[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, rg = wave & 3, cx = wave >> 2;
+    const int tiles_x = (a.Wo + DTX - 1) / DTX, tiles_y = (a.Ho + DTY - 1) / DTY;
+    int t = blockIdx.x;
+    const int tx0 = (t % tiles_x) * DTX;
+    t /= tiles_x;
+    const int ty0 = (t % tiles_y) * DTY;
+    const int b = t / tiles_y;
+    const int n0 = blockIdx.y * 64;
+    if (a.st && !(a.st[a.rhs0 + b].active && !a.st[a.rhs0 + b].cycdone)) return;
+    if (wc && tid == 0) {
+        const int my = a.Ho - ty0 < DTY ? a.Ho - ty0 : DTY, mx = a.Wo - tx0 < DTX ? a.Wo - tx0 : DTX;
+        const int nr = a.N - n0 < 64 ? a.N - n0 : 64;
+        work_atomic(wc, 2ull * my * mx * nr * (unsigned long long)(9 * (a.c1 + a.c2)));
+    }
+    if (tid < 64) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[n0 + tid] : 0.f;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    DlStage ds;
+    ds.tile(a, lane, wave, ty0, tx0, 0 >= a.c1);
+    ds.wset(a, lane, wave, n0);
+    const int nchunk = (a.c1 + a.c2) / HC;
+    ds.issue(a, wave, b, 0, stage0);
+    // chunk ch is multiplied out of cur while chunk ch + 1 loads into next
+    auto step = [&](int ch, unsigned char* next, const unsigned char* cur) {
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of chunk ch have landed
+        __syncthreads();                 // everyone's have, and nobody still reads the other stage
+        if (ch + 1 < nchunk) {
+            const int c0 = (ch + 1) * HC;
+            if (c0 == a.c1) ds.tile(a, lane, wave, ty0, tx0, 1);
+            ds.issue(a, wave, b, c0, next);
+        }
+        const bf16* P = reinterpret_cast<const bf16*>(cur);
+        dl_mma(P, P + DPBYTES / 2, acc, lane, rg, cx);
+    };
+    for (int ch = 0; ch < nchunk; ch += 2) {
+        step(ch, stage1, stage0);
+        if (ch + 1 < nchunk) step(ch + 1, stage0, stage1);
+    }
+    __syncthreads();   // both stages free for the epilogue
+    dl_epilogue(a, acc, b, ty0, tx0, n0, tid, reinterpret_cast<bf16*>(stage0), bias_s);
+}
+
 // Persistent form for layers of NCH * 32 input channels (NCH = 1, 2) and at most
 // BN output channels: the block loads all its weights into LDS once, walks over
 // (tile, chunk) items with a stride of gridDim.x tiles, and prefetches the next
@@ -1379,7 +1626,7 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // tuned (accumulating ones would add each candidate's result).
 enum ConvKernel {
     CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W,
-    CK_PERS16, CK_COUNT
+    CK_PERS16, CK_DL64, CK_COUNT
 };
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
@@ -1394,6 +1641,7 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_GEMM64W: return a.N >= 128;
         case CK_GEMM128W: return a.N >= 64;
         case CK_PERS16: return halo && a.N <= 16 && C == HC;   // narrow outputs (the 2-channel head)
+        case CK_DL64: return halo && a.N > 32 && a.gmode == G_CONV;   // forward only
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1422,6 +1670,13 @@ static void launch_halo_ck(const GemmArgs& a, hipStream_t s, unsigned long long*
         launch_pers<16, FLIP, EPI, 1>(a, s, wc);
     } else if (ck == CK_HALO32) {
         launch_single<32, FLIP, EPI>(a, s, wc);
+    } else if (ck == CK_DL64) {
+        if constexpr (FLIP == 0 && EPI == E_FWD) {
+            const int ntiles = ((a.Ho + DTY - 1) / DTY) * ((a.Wo + DTX - 1) / DTX) * a.B;
+            TIMED_LAUNCH("k_conv", s, k_conv3_dl, dim3(ntiles, (a.N + 63) / 64), dim3(512), 0, s, a, wc);
+        } else {
+            launch_single<64, FLIP, EPI>(a, s, wc);   // not applicable (ck_applicable excludes it)
+        }
     } else {
         launch_single<64, FLIP, EPI>(a, s, wc);
     }
@@ -1433,6 +1688,7 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
         case CK_PERS16:
         case CK_HALO32:
         case CK_HALO64:
+        case CK_DL64:
             if (a.gmode == G_CONVT)
                 launch_halo_ck<1, E_ACC>(a, s, wc, ck);
             else

@@ -411,7 +411,9 @@ __global__ __launch_bounds__(256) void k_poly_term(const cx<T>* __restrict__ src
 // registers.  The residual is double buffered in LDS, so one barrier per
 // factor suffices: a thread overwrites buffer (t+1) % 2 only after the barrier
 // of factor t, which every thread reaches after its reads of factor t-1 from
-// that buffer.  Used when the level has at most POLY_LDS_MAX nodes.
+// that buffer.  The factors' reciprocal roots are formed once, into LDS, at the
+// start (a global load and two divisions per factor otherwise sit on every
+// factor's critical path).  Used when the level has at most POLY_LDS_MAX nodes.
 template <typename T>
 __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restrict__ src, cx<T>* __restrict__ out,
                                                            const c128* __restrict__ sl, int nz, int nx,
@@ -428,6 +430,12 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
     out += (long)rl * N;
     add_work(wc, (unsigned long long)N * 2 * sizeof(cx<T>));
     extern __shared__ c128 lds_poly[];   // two residual buffers of N entries
+    __shared__ c128 inv_roots[64];       // 1 / theta_t, formed once (deg <= 64)
+    if (threadIdx.x < deg) {
+        const c128 th = roots[threadIdx.x];
+        const double d = th.re * th.re + th.im * th.im;
+        inv_roots[threadIdx.x] = mk(th.re / d, -th.im / d);
+    }
     c128 xr[POLY_NPT], rr[POLY_NPT], sd[POLY_NPT];
     int ii[POLY_NPT], kk[POLY_NPT];
 #pragma unroll
@@ -444,10 +452,9 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
             sd[q] = mk(ns.dg - sl[n].re, -sl[n].im);
         }
     }
+    __syncthreads();
     for (int t = 0; t < deg; ++t) {
-        c128 th = roots[t];
-        double d = th.re * th.re + th.im * th.im;
-        c128 it = mk(th.re / d, -th.im / d);
+        const c128 it = inv_roots[t];
 #pragma unroll
         for (int q = 0; q < POLY_NPT; ++q) xr[q] = xr[q] + rr[q] * it;
         if (t == deg - 1) break;

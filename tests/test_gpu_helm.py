@@ -43,10 +43,11 @@ def test_matvec_parity(gpu, nz, nx, adjoint):
     assert relerr(v128, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("nz,nx", [(64, 64), (128, 128), (96, 96), (70, 34), (272, 260)])
+@pytest.mark.parametrize("nz,nx", [(64, 64), (128, 128), (96, 96), (70, 34), (256, 256), (120, 264), (272, 260)])
 def test_vcycle_parity(gpu, nz, nx):
     """(272, 260) has a 68 x 65 coarsest level: the per-factor polynomial
-    kernels; the others fit the single-workgroup LDS kernel."""
+    kernels; the others (up to the bench's 64 x 64, and a 30 x 66 one) fit the
+    single-workgroup LDS kernel."""
     print(f"vcycle {nz}x{nx}", flush=True)
     med = medium(nz, nx, seed=nz + nx)
     H = setup(med)

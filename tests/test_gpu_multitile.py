@@ -17,6 +17,7 @@ from paper_2405_17696_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 CK_PERS = 0     # the persistent halo kernel's id for helm_conv_force
+CK_DL64 = 10    # the double-buffered direct-load kernel, one 16 x 32 tile per block
 
 
 def bf(x):
@@ -51,6 +52,36 @@ def test_persistent_conv_many_tiles_per_block(gpu, c2, bcast):
             assert relerr(y[s, t:t + 16], ref[s, t:t + 16]) <= 1e-5
 
 
+@pytest.mark.parametrize("c2,bcast,cout,use_resid", [(0, False, 64, False), (64, True, 64, False),
+                                                     (0, False, 128, True)])
+def test_direct_load_conv_many_tiles(gpu, c2, bcast, cout, use_resid):
+    """The direct-load kernel on 64-channel layers (plain, concatenated broadcast
+    context, 128 outputs with a residual) over 9 samples of 128 x 128: 288 tiles
+    of 16 x 32, more than can be resident at once."""
+    Bn, H, W_ = 9, 128, 128
+    ck = CK_DL64
+    print("direct-load conv, c2", c2, "cout", cout, flush=True)
+    x1 = rnd((Bn, H, W_, 64), 51)
+    x2 = rnd((1, H, W_, c2), 52) if c2 else None
+    Wt = rnd((cout, 3, 3, 64 + c2), 53, scale=np.sqrt(2.0 / (9 * (64 + c2))))
+    b = rnd((cout,), 54, 0.1)
+    resid = rnd((Bn, H, W_, cout), 55) if use_resid else None
+    api.helm_conv_force(ck)
+    try:
+        y = api.cnn_layer_forward(0, 1, x1, Wt, b, x2=x2, bcast2=bcast, resid=resid, relu=not use_resid)
+    finally:
+        api.helm_conv_force(-1)
+    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])], axis=-1)
+    ref = U.conv3x3(x, Wt, b, 1)
+    ref = ref + resid if use_resid else np.maximum(ref, 0)
+    e = relerr(y, ref)
+    print("rel err", e)
+    assert e <= 1e-5
+    for s in range(Bn):
+        for t in range(0, H, 16):
+            assert relerr(y[s, t:t + 16], ref[s, t:t + 16]) <= 1e-5
+
+
 def test_fused_resblock_many_tiles_per_block(gpu):
     Bn, H, W_ = 4, 256, 256
     print("resblock multi-tile", flush=True)
@@ -74,7 +105,8 @@ def test_precond_apply_full_width_full_size(gpu):
     """M_net(r) at 256 x 256, batch 2, default widths, He-normal weights at full
     scale (no damped head) and small random biases: the inference path with the
     fused first layer + context convolution and the fused residual blocks, over
-    1024 level-0 tiles per launch."""
+    1024 level-0 tiles per launch; with the built-in kernel choice and with the
+    64-channel layers pinned to the direct-load kernel."""
     med, _ = synth.config2_medium()
     k2, gam = f32(med.kappa2), f32(med.gamma)
     widths = (32, 64, 128, 256)
@@ -92,8 +124,17 @@ def test_precond_apply_full_width_full_size(gpu):
     H = api.helm_setup(torch.tensor(k2, dtype=torch.float32, device="cuda"),
                        torch.tensor(gam, dtype=torch.float32, device="cuda"), med.omega, med.h)
     r = rand_c((2, 256, 256), 53).astype(np.complex64)
-    print("precond apply full size", flush=True)
-    e = api.cnn_precond_apply(net, H, torch.tensor(r, device="cuda")).cpu().numpy()
+    # the built-in kernel choice, then the 64-channel layers on the direct-load kernel (its bf16
+    # outputs leave through the LDS epilogue)
+    outs = {}
+    try:
+        for ck in (-1, CK_DL64):
+            print("precond apply full size, kernel", ck, flush=True)
+            api.helm_conv_force(ck)
+            outs[ck] = api.cnn_precond_apply(net, H, torch.tensor(r, device="cuda")).cpu().numpy()
+    finally:
+        api.helm_conv_force(-1)
+    e = outs[-1]
     rr = r.astype(np.complex128)
     ref = U.cnn_precond(theta, k2, gam, med.omega, med.h, med.h, rr, widths, 2)
     orig = U.Net
@@ -109,4 +150,8 @@ def test_precond_apply_full_width_full_size(gpu):
     assert e64 <= 2e-2
     for s in range(2):
         assert relerr(e[s], ref[s]) <= 2e-2
+    for ck in (CK_DL64,):
+        print("kernel", ck, "rel err vs FP64", relerr(outs[ck], ref), "vs BF16-storage oracle", relerr(outs[ck], emu))
+        for s in range(2):
+            assert relerr(outs[ck][s], ref[s]) <= 2e-2
 
