@@ -406,6 +406,7 @@ constexpr int HC = 32;              // channels per chunk
 constexpr int HLD = HC + 8;         // padded LDS row (bf16)
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
 // 16-byte raw buffer load; an offset at or past the descriptor's byte count reads zeros.
 __device__ __forceinline__ bf16x8 bload8(__amdgpu_buffer_rsrc_t r, unsigned off) {
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -679,26 +680,30 @@ __device__ __forceinline__ void halo_epilogue_lds(const GemmArgs& a, const f32x4
     __syncthreads();
     // a residual is added here on whole 16-byte rows: convolution plus bias is rounded to bf16
     // above, the sum with the residual is rounded again
+    // every thread issues CPP stores (pixels outside the image are written past the end of the
+    // output, which the buffer's range check drops): with a fixed count the persistent kernels'
+    // wait for their next tile's prefetched loads need not wait for these stores as well
     constexpr int CPP = BN / 8;                   // 16-byte chunks per pixel
+    const unsigned nrec = (unsigned)((long)a.B * a.Ho * a.Wo * a.N * 2);
+    const __amdgpu_buffer_rsrc_t ro = brsrc(a.out, nrec);
 #pragma unroll
     for (int r = 0; r < CPP; ++r) {
         const int k = tid + r * 256;
         const int p = k / CPP, c = k - p * CPP;
         const int y = ty0 + p / HT, xx = tx0 + (p & (HT - 1)), n = n0 + c * 8;
-        if (y < a.Ho && xx < a.Wo && n < a.N) {
-            const long o = (((long)b * a.Ho + y) * a.Wo + xx) * a.N + n;
-            bf16x8 t = *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
-            if (a.resid) {
-                const bf16x8 rr = *reinterpret_cast<const bf16x8*>(a.resid + o);
+        const bool ok = y < a.Ho && xx < a.Wo && n < a.N;
+        const unsigned off = ok ? (unsigned)(((((long)b * a.Ho + y) * a.Wo + xx) * a.N + n) * 2) : nrec;
+        bf16x8 t = *reinterpret_cast<const bf16x8*>(scratch + p * SP + c * 8);
+        if (a.resid) {
+            const bf16x8 rr = bload8(brsrc(a.resid, nrec), off);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    float w = (float)t[e] + (float)rr[e];
-                    if (a.relu) w = w > 0.f ? w : 0.f;
-                    t[e] = (bf16)w;
-                }
+            for (int e = 0; e < 8; ++e) {
+                float w = (float)t[e] + (float)rr[e];
+                if (a.relu) w = w > 0.f ? w : 0.f;
+                t[e] = (bf16)w;
             }
-            *reinterpret_cast<bf16x8*>(a.out + o) = t;
         }
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4s, t), ro, off, 0, 0);
     }
     __syncthreads();
 }
@@ -1020,8 +1025,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCH == 1 ? 
     const int tps = tiles_x * tiles_y;
     const int ntiles = a.B * tps;
     const int n0 = blockIdx.y * BN;
+    // the samples' RHS flags, read once into LDS: a global load in the tile loop would make the
+    // wave wait for all of its outstanding memory operations, the previous tile's stores included
+    __shared__ unsigned char live_s[256];
+    const bool flags_lds = a.st && a.B <= 256;
+    if (flags_lds)
+        for (int i = tid; i < a.B; i += 256) live_s[i] = a.st[a.rhs0 + i].active && !a.st[a.rhs0 + i].cycdone;
+    __syncthreads();
     auto next_tile = [&](int t) {
-        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+        while (t < ntiles && a.st &&
+               !(flags_lds ? live_s[t / tps] : a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
             t += gridDim.x;
         return t;
     };
@@ -1295,8 +1308,16 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (a.W + RT - 1) / RT, tiles_y = (a.H + RT - 1) / RT, tps = tiles_x * tiles_y;
     const int ntiles = a.B * tps;
+    // the samples' RHS flags, read once into LDS: a global load in the tile loop would make the
+    // wave wait for all of its outstanding memory operations, the previous tile's stores included
+    __shared__ unsigned char live_s[256];
+    const bool flags_lds = a.st && a.B <= 256;
+    if (flags_lds)
+        for (int i = tid; i < a.B; i += 256) live_s[i] = a.st[a.rhs0 + i].active && !a.st[a.rhs0 + i].cycdone;
+    __syncthreads();
     auto next_tile = [&](int t) {
-        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+        while (t < ntiles && a.st &&
+               !(flags_lds ? live_s[t / tps] : a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
             t += gridDim.x;
         return t;
     };
@@ -1411,12 +1432,22 @@ __global__ __launch_bounds__(256) void k_resblock32(ResArgs a, unsigned long lon
             }
         }
         __syncthreads();
-        for (int k = tid; k < RT * RT * 4; k += 256) {
-            const int p = k >> 2, c = k & 3;
-            const int y = oy0 + p / RT, x = ox0 + p % RT;
-            if (y < a.H && x < a.W)
-                *reinterpret_cast<bf16x8*>(a.out + (((long)b * a.H + y) * a.W + x) * 32 + c * 8) =
-                    *reinterpret_cast<const bf16x8*>(ob + p * OSP + c * 8);
+        // a fixed number of stores per thread (pixels outside the image or past the tile are
+        // written past the end of the buffer, which the buffer's range check drops), so that
+        // the wait for the next tile's prefetched patch need not also wait for these stores
+        {
+            const unsigned nrec = (unsigned)((long)a.B * a.H * a.W * 32 * 2);
+            const __amdgpu_buffer_rsrc_t ro = brsrc(a.out, nrec);
+#pragma unroll
+            for (int r = 0; r < (RT * RT * 4 + 255) / 256; ++r) {
+                const int k = tid + r * 256;
+                const int p = k >> 2, c = k & 3;
+                const int y = oy0 + p / RT, x = ox0 + p % RT;
+                const bool ok = k < RT * RT * 4 && y < a.H && x < a.W;
+                const unsigned off = ok ? (unsigned)(((((long)b * a.H + y) * a.W + x) * 32 + c * 8) * 2) : nrec;
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(ob + (ok ? p : 0) * OSP + c * 8);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4s, v), ro, off, 0, 0);
+            }
         }
         if (wc) {
             const int my = a.H - oy0 < RT ? a.H - oy0 : RT, mx = a.W - ox0 < RT ? a.W - ox0 : RT;
@@ -1444,8 +1475,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (a.W + HT - 1) / HT, tiles_y = (a.H + HT - 1) / HT, tps = tiles_x * tiles_y;
     const int ntiles = a.B * tps;
+    // the samples' RHS flags, read once into LDS (see k_conv3_pers)
+    __shared__ unsigned char live_s[256];
+    const bool flags_lds = a.st && a.B <= 256;
+    if (flags_lds)
+        for (int i = tid; i < a.B; i += 256) live_s[i] = a.st[a.rhs0 + i].active && !a.st[a.rhs0 + i].cycdone;
+    __syncthreads();
     auto next_tile = [&](int t) {
-        while (t < ntiles && a.st && !(a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
+        while (t < ntiles && a.st &&
+               !(flags_lds ? live_s[t / tps] : a.st[a.rhs0 + t / tps].active && !a.st[a.rhs0 + t / tps].cycdone))
             t += gridDim.x;
         return t;
     };
@@ -1470,6 +1508,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         tx0 = (tt % tiles_x) * HT;
     };
     unsigned rr[2];
+    // two 4-byte loads per thread and tile, always issued (pixels outside the image or the patch
+    // read past the end of the input and get zeros), so that their count is fixed
+    const unsigned rrec = (unsigned)((long)a.B * a.H * a.W * 2 * 2);
+    const __amdgpu_buffer_rsrc_t rsr = brsrc(a.r, rrec);
     auto rload = [&](int tt) {
         int b, ty0, tx0;
         origin(tt, b, ty0, tx0);
@@ -1478,12 +1520,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             const int idx = tid + q * 256;
             const int py = idx / RP, px = idx - py * RP;
             const int yi = ty0 - 2 + py, xi = tx0 - 2 + px;
-            rr[q] = idx < RP * RP && yi >= 0 && yi < a.H && xi >= 0 && xi < a.W
-                        ? *reinterpret_cast<const unsigned*>(a.r + (((long)b * a.H + yi) * a.W + xi) * 2)
-                        : 0u;
+            const bool in = idx < RP * RP && yi >= 0 && yi < a.H && xi >= 0 && xi < a.W;
+            rr[q] = __builtin_amdgcn_raw_buffer_load_b32(rsr, in ? (unsigned)((((long)b * a.H + yi) * a.W + xi) * 4) : rrec,
+                                                         0, 0);
         }
     };
     GemmArgs g{};   // the epilogue's view of the output
+    g.B = a.B;
     g.Ho = a.H;
     g.Wo = a.W;
     g.N = 32;
@@ -1580,6 +1623,8 @@ static bool halo_ok(const GemmArgs& a) {
     // the staging addresses one sample's input half and the weights with 32-bit byte offsets
     if ((long)a.Hi * a.Wi * std::max(a.c1, a.c2) * 2 + 4096 >= (1L << 31)) return false;
     if ((long)a.N * a.K * 2 >= (1L << 31)) return false;
+    // and the epilogue addresses the output (and a residual) with 32-bit byte offsets
+    if ((long)a.B * a.Ho * a.Wo * a.N * 2 >= (1L << 31)) return false;
     return a.K >= 9 * (a.c1 + a.c2);
 }
 
