@@ -1010,6 +1010,165 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     dl_epilogue(a, acc, b, ty0, tx0, n0, tid, reinterpret_cast<bf16*>(stage0), bias_s);
 }
 
+// ------------------------------------------------------------------ persistent up-convolution
+// Forward 2x2 stride-2 transposed convolution as a GEMM D[M x N] = A[M x K] W^T
+// (M input pixels, K = C_in, N = 4 C_out: column n is phase (n / C_out) of output
+// channel n % C_out).  The implicit GEMM reloads a block's 128 x K weight slab
+// for every 64 pixels, which at these shapes is most of its memory traffic;
+// here a block keeps its slab in LDS for the whole launch and walks 64-pixel
+// tiles (blockIdx.x, + gridDim.x, ...), the next tile's pixels loaded into
+// registers while the current one is multiplied and written out through LDS.
+constexpr int UP_BM = 64, UP_BN = 128;
+// F32 = true also writes the FP32 copy of the output (the layer tests); kept out of the bf16-only
+// form so that its tile loop issues a fixed number of stores.
+template <int K, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 64 ? 2 : 1))) void k_upconv(GemmArgs a,
+                                                                                                       unsigned long long* wc) {
+    constexpr int KP = K + 8;                       // padded LDS row (bf16)
+    constexpr int ASEG = UP_BM * K / 8;             // 16-byte segments of a pixel tile
+    constexpr int APT = (ASEG + 255) / 256;
+    constexpr int OSP = UP_BN + 8;                  // output staging row (bf16)
+    __shared__ __attribute__((aligned(16))) bf16 Ws[UP_BN][KP];
+    __shared__ __attribute__((aligned(16))) bf16 As[2][UP_BM][KP];
+    __shared__ __attribute__((aligned(16))) bf16 Os[UP_BM][OSP];
+    __shared__ __attribute__((aligned(16))) float bias_s[UP_BN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;        // wave tile: 32 pixels x 64 columns
+    const int n0 = blockIdx.y * UP_BN;
+    const int cout = a.N >> 2;
+    const long ntm = (a.M + UP_BM - 1) / UP_BM;
+    // skip tiles of samples whose RHS is inactive (a tile lies in one sample when Ho Wo % 64 == 0)
+    const long hw = (long)a.Ho * a.Wo;
+    // the samples' RHS flags, read once into LDS: a global load in the tile loop would make the
+    // wave wait for all of its outstanding memory operations, the previous tile's stores included
+    __shared__ unsigned char live_s[256];
+    const bool skip_ok = a.st && hw % UP_BM == 0 && a.B <= 256;
+    if (skip_ok)
+        for (int i = tid; i < a.B; i += 256) live_s[i] = a.st[a.rhs0 + i].active && !a.st[a.rhs0 + i].cycdone;
+    __syncthreads();
+    auto live = [&](long mt) { return !skip_ok || live_s[(int)(mt * UP_BM / hw)]; };
+    auto next_tile = [&](long mt) {
+        while (mt < ntm && !live(mt)) mt += gridDim.x;
+        return mt;
+    };
+    long mt = next_tile(blockIdx.x);
+    if (mt >= ntm) return;   // the same decision for every thread of the block
+    for (int sg = tid; sg < UP_BN * (K / 8); sg += 256) {
+        const int row = sg / (K / 8), sub = sg - row * (K / 8);
+        *reinterpret_cast<bf16x8*>(&Ws[row][sub * 8]) =
+            n0 + row < a.N ? ld8(a.w + (long)(n0 + row) * a.K + sub * 8) : zero8();
+    }
+    if (tid < UP_BN) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[(n0 + tid) % cout] : 0.f;
+    const unsigned arec = (unsigned)((long)a.M * K * 2);
+    const __amdgpu_buffer_rsrc_t ra = brsrc(a.a1, arec);   // input pixels [M][K] (one sample after another)
+    bf16x8 ra_v[APT];
+    auto issue = [&](long t) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            const int sg = tid + q * 256;
+            const int row = sg / (K / 8), sub = sg - row * (K / 8);
+            const long m = t * UP_BM + row;
+            ra_v[q] = bload8(ra, sg < ASEG && m < a.M ? (unsigned)((m * K + sub * 8) * 2) : arec);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg < ASEG) {
+                const int row = sg / (K / 8), sub = sg - row * (K / 8);
+                *reinterpret_cast<bf16x8*>(&As[buf][row][sub * 8]) = ra_v[q];
+            }
+        }
+    };
+    const unsigned orec = (unsigned)((long)a.B * 4 * hw * cout * 2);
+    const __amdgpu_buffer_rsrc_t ro = brsrc(a.out, orec);
+    unsigned long long work = 0;
+    issue(mt);
+    int buf = 0;
+    while (true) {
+        store(buf);
+        __syncthreads();   // the tile is in As[buf]; the previous tile's output staging has been read
+        const long mn = next_tile(mt + gridDim.x);
+        if (mn < ntm) issue(mn);
+        f32x4 acc[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            bf16x8 fa[2], fb[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 32 + i * 16 + (lane & 15)][k0 + (lane >> 4) * 8]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8*>(&Ws[wn * 64 + j * 16 + (lane & 15)][k0 + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j], fa[i], acc[i][j], 0, 0, 0);
+        }
+        // acc[i][j][e]: pixel wm*32 + 16 i + l%16, column wn*64 + 16 j + 4 (l/16) + e
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ml = wm * 32 + i * 16 + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int nl = wn * 64 + j * 16 + (lane >> 4) * 4;
+                const float4 bb = *reinterpret_cast<const float4*>(bias_s + nl);
+                f32x4 v = acc[i][j];
+                v[0] += bb.x;
+                v[1] += bb.y;
+                v[2] += bb.z;
+                v[3] += bb.w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = a.relu && v[e] < 0.f ? 0.f : v[e];
+                bf16x4 o;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+                *reinterpret_cast<bf16x4*>(&Os[ml][nl]) = o;
+                const long m = mt * UP_BM + ml;
+                const int n = n0 + nl;
+                if (F32 && m < a.M && n < a.N) {
+                    const Pix p = pix_of(m, a.Ho, a.Wo);
+                    const int ad = n / cout, co = n - ad * cout;
+                    *reinterpret_cast<f32x4*>(
+                        a.outf + (((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) * cout + co) = v;
+                }
+            }
+        }
+        __syncthreads();
+        // 64 pixels x 128 columns in 16-byte groups, four per thread, always issued (groups past
+        // M or N get an offset past the end of the output, which the range check drops)
+#pragma unroll
+        for (int r = 0; r < UP_BM * UP_BN / 8 / 256; ++r) {
+            const int k = tid + r * 256;
+            const int ml = k / (UP_BN / 8), c = k - ml * (UP_BN / 8);
+            const long m = mt * UP_BM + ml;
+            const int n = n0 + c * 8;
+            unsigned off = orec;
+            if (m < a.M && n < a.N) {
+                const Pix p = pix_of(m, a.Ho, a.Wo);
+                const int ad = n / cout, co = n - ad * cout;
+                off = (unsigned)(((((long)p.b * 2 * a.Ho + 2 * p.y + (ad >> 1)) * (2 * a.Wo) + 2 * p.x + (ad & 1)) * cout + co) * 2);
+            }
+            __builtin_amdgcn_raw_buffer_store_b128(
+                __builtin_bit_cast(u32x4s, *reinterpret_cast<const bf16x8*>(&Os[ml][c * 8])), ro, off, 0, 0);
+        }
+        if (wc) {
+            const long mr = a.M - mt * UP_BM < UP_BM ? a.M - mt * UP_BM : UP_BM;
+            const int nr = a.N - n0 < UP_BN ? a.N - n0 : UP_BN;
+            work += 2ull * (unsigned long long)mr * nr * K;
+        }
+        if (mn >= ntm) break;
+        mt = mn;
+        buf ^= 1;
+    }
+    if (wc && tid == 0) work_atomic(wc, work);
+}
+
 // Persistent form for layers of NCH * 32 input channels (NCH = 1, 2) and at most
 // BN output channels: the block loads all its weights into LDS once, walks over
 // (tile, chunk) items with a stride of gridDim.x tiles, and prefetches the next
@@ -1671,8 +1830,30 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // tuned (accumulating ones would add each candidate's result).
 enum ConvKernel {
     CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W,
-    CK_PERS16, CK_DL64, CK_COUNT
+    CK_PERS16, CK_DL64, CK_UPP, CK_COUNT
 };
+
+// The persistent up-convolution: K = C_in of 64, 128 or 256, contiguous input, C_out a multiple
+// of 8, 32-bit byte offsets.
+static bool upconv_ok(const GemmArgs& a) {
+    if (a.gmode != G_UP || a.epi != E_UPFWD || !a.out || a.c2 != 0 || a.resid || a.bmap) return false;
+    if (!(a.K == a.c1 && (a.c1 == 64 || a.c1 == 128 || a.c1 == 256))) return false;
+    if (a.abs1 != (long)a.Hi * a.Wi * a.c1 || a.Ho != a.Hi || a.Wo != a.Wi || (a.N & 31) != 0) return false;
+    return (long)a.M * a.K * 2 < (1L << 31) && (long)a.M * a.N * 2 < (1L << 31);
+}
+
+template <int K>
+static void launch_upconv_k(const GemmArgs& a, hipStream_t s, unsigned long long* wc) {
+    static int res = 0;
+    const long ntm = (a.M + UP_BM - 1) / UP_BM;
+    const int ny = (a.N + UP_BN - 1) / UP_BN;
+    const int slots = resident_blocks(k_upconv<K, false>, res);
+    const int gx = (int)std::max<long>(1, std::min<long>(ntm, std::max(1, slots / ny)));
+    if (a.outf)
+        TIMED_LAUNCH("k_conv", s, (k_upconv<K, true>), dim3(gx, ny), dim3(256), 0, s, a, wc);
+    else
+        TIMED_LAUNCH("k_conv", s, (k_upconv<K, false>), dim3(gx, ny), dim3(256), 0, s, a, wc);
+}
 
 static bool ck_applicable(const GemmArgs& a, int ck) {
     const bool halo = halo_ok(a);
@@ -1687,6 +1868,7 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_GEMM128W: return a.N >= 64;
         case CK_PERS16: return halo && a.N <= 16 && C == HC;   // narrow outputs (the 2-channel head)
         case CK_DL64: return halo && a.N > 32 && a.gmode == G_CONV;   // forward only
+        case CK_UPP: return upconv_ok(a);
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1738,6 +1920,13 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
                 launch_halo_ck<1, E_ACC>(a, s, wc, ck);
             else
                 launch_halo_ck<0, E_FWD>(a, s, wc, ck);
+            break;
+        case CK_UPP:
+            switch (a.c1) {
+                case 64: launch_upconv_k<64>(a, s, wc); break;
+                case 128: launch_upconv_k<128>(a, s, wc); break;
+                default: launch_upconv_k<256>(a, s, wc); break;
+            }
             break;
         case CK_FIRST2: {
             const long nseg = (long)a.B * a.Ho * ((a.Wo + 15) / 16);

@@ -146,6 +146,7 @@ FORCE_CASES = [
     ("s2_wide", 0, 2, 1, 16, 16, 128, 0, False, 256, True, False),
     ("up", 1, 2, 2, 9, 10, 128, 0, False, 64, True, False),
     ("up_wide", 1, 2, 1, 8, 8, 256, 0, False, 128, True, False),
+    ("up64", 1, 2, 3, 19, 13, 64, 0, False, 32, True, False),      # 741 pixels: 12 tiles of 64, ragged
 ]
 
 
