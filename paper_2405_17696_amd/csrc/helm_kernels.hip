@@ -486,6 +486,111 @@ __global__ __launch_bounds__(POLY_THREADS) void k_poly_lds(const cx<T>* __restri
     }
 }
 
+// Whole-wave DPP lane shifts (lane l receives the value of lane l - 1, resp.
+// l + 1; the lane without a source receives zero), on the two 32-bit halves of
+// each double.
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ c128 lane_shift(c128 v) {
+    return mk(lane_shift<CTRL>(v.re), lane_shift<CTRL>(v.im));
+}
+
+// The same polynomial for levels of at most 64 x 64 nodes (the coarsest level of
+// a 256 x 256 grid with three levels), laid out by rows: wave w of the
+// 1024-thread workgroup holds rows PW_ROWS w .. PW_ROWS w + 3, lane k column k.
+// A node's west and east neighbours then come from the adjacent lanes by DPP
+// shifts and its north and south ones from the thread's own registers; only the
+// strips' edge rows cross waves, through LDS (each wave writes its top and
+// bottom rows, double buffered as in k_poly_lds, one barrier per factor, and
+// reads the rows next to its strip).  Per thread and factor that is 2 LDS
+// writes and 2 reads where k_poly_lds has 4 and 16.  The per-node arithmetic,
+// its order and the boundary coefficients are those of k_poly_lds; lanes and
+// rows outside the level hold zeros throughout.
+constexpr int PW_ROWS = 4, PW_WAVES = POLY_THREADS / 64, PW_MAXNX = 64, PW_MAXNZ = PW_WAVES * PW_ROWS;
+template <typename T>
+__global__ __launch_bounds__(POLY_THREADS) void k_poly_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ out,
+                                                            const c128* __restrict__ sl, int nz, int nx,
+                                                            Sten<double> sten, const c128* __restrict__ roots,
+                                                            int deg, const RhsState* __restrict__ st, int rhs0,
+                                                            unsigned long long* wc) {
+    const int rl = blockIdx.x;
+    if (st) {
+        const RhsState& S = st[rhs0 + rl];
+        if (!S.active || S.cycdone) return;
+    }
+    const int N = nz * nx;
+    src += (long)rl * N;
+    out += (long)rl * N;
+    add_work(wc, (unsigned long long)N * 2 * sizeof(cx<T>));
+    __shared__ c128 inv_roots[64];                  // 1 / theta_t (deg <= 64)
+    __shared__ c128 edge[2][PW_WAVES][2][64];       // [buffer][wave][top, bottom row][column]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < deg) {
+        const c128 th = roots[threadIdx.x];
+        const double d = th.re * th.re + th.im * th.im;
+        inv_roots[threadIdx.x] = mk(th.re / d, -th.im / d);
+    }
+    const c128 zero = mk(0.0, 0.0);
+    c128 xr[PW_ROWS], rr[PW_ROWS], sd[PW_ROWS];
+    double cn[PW_ROWS];
+    bool ok[PW_ROWS];
+    const double cw = lane == nx - 1 ? sten.axl : sten.ax;
+#pragma unroll
+    for (int q = 0; q < PW_ROWS; ++q) {
+        const int i = wave * PW_ROWS + q, n = i * nx + lane;
+        ok[q] = lane < nx && i < nz;
+        cn[q] = i == nz - 1 ? sten.azl : sten.az;
+        xr[q] = zero;
+        rr[q] = zero;
+        sd[q] = zero;
+        if (ok[q]) {
+            rr[q] = ccast<double>(src[n]);
+            // stencil diagonal minus the mass term
+            NodeSten<double> ns = node_sten(sten, i, lane, nz, nx);
+            sd[q] = mk(ns.dg - sl[n].re, -sl[n].im);
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < deg; ++t) {
+        const c128 it = inv_roots[t];
+#pragma unroll
+        for (int q = 0; q < PW_ROWS; ++q) xr[q] = xr[q] + rr[q] * it;
+        if (t == deg - 1) break;
+        c128(*eb)[2][64] = edge[t & 1];
+        eb[wave][0][lane] = rr[0];
+        eb[wave][1][lane] = rr[PW_ROWS - 1];
+        c128 wv[PW_ROWS], ev[PW_ROWS];
+#pragma unroll
+        for (int q = 0; q < PW_ROWS; ++q) {
+            wv[q] = lane_shift<DPP_WAVE_SHR1>(rr[q]);
+            ev[q] = lane_shift<DPP_WAVE_SHL1>(rr[q]);
+        }
+        __syncthreads();
+        const c128 above = wave > 0 ? eb[wave - 1][1][lane] : zero;
+        const c128 below = wave + 1 < PW_WAVES ? eb[wave + 1][0][lane] : zero;
+        c128 rn[PW_ROWS];
+#pragma unroll
+        for (int q = 0; q < PW_ROWS; ++q) {
+            const c128 nn = q > 0 ? rr[q - 1] : above;
+            const c128 sv = q + 1 < PW_ROWS ? rr[q + 1] : below;
+            c128 pr = sd[q] * rr[q] - cw * wv[q] - sten.ax * ev[q] - cn[q] * nn - sten.az * sv;
+            rn[q] = ok[q] ? rr[q] - pr * it : zero;
+        }
+#pragma unroll
+        for (int q = 0; q < PW_ROWS; ++q) rr[q] = rn[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PW_ROWS; ++q)
+        if (ok[q]) out[(wave * PW_ROWS + q) * nx + lane] = ccast<T>(xr[q]);
+}
+
 template <typename T>
 static const cx<T>* sl_of(const Level& L) {
     if constexpr (sizeof(T) == 4)
@@ -540,7 +645,12 @@ int launch_vcycle(const helm_op* op, const cx<T>* f, const double* fscale, int f
             c128* xw = w.xw + (long)r0 * n;
             if (l == 0 && (fscale || addend))
                 return fail(HELM_EINVAL, "single-level cycle does not take scaled or offset inputs");
-            if (n <= POLY_LDS_MAX && op->roots_dev && op->poly_lds_ok) {
+            if (C.nx <= PW_MAXNX && C.nz <= PW_MAXNZ && op->roots_dev) {
+                TIMED_LAUNCH("k_poly_rows", s, k_poly_rows<T>, dim3(nr), dim3(POLY_THREADS), 0, s, src, xdst, C.sl64,
+                             C.nz, C.nx, C.sten<double>(), op->roots_dev, deg, st, rhs0 + r0,
+                             WORK_COUNTER("k_poly_rows", s));
+                HELM_CHECK_LAUNCH();
+            } else if (n <= POLY_LDS_MAX && op->roots_dev && op->poly_lds_ok) {
                 size_t lds = 2 * (size_t)n * sizeof(c128);
                 TIMED_LAUNCH("k_poly_lds", s, k_poly_lds<T>, dim3(nr), dim3(POLY_THREADS), lds, s, src, xdst, C.sl64,
                              C.nz, C.nx, C.sten<double>(), op->roots_dev, deg, st, rhs0 + r0,

@@ -46,8 +46,9 @@ def test_matvec_parity(gpu, nz, nx, adjoint):
 @pytest.mark.parametrize("nz,nx", [(64, 64), (128, 128), (96, 96), (70, 34), (256, 256), (120, 264), (272, 260)])
 def test_vcycle_parity(gpu, nz, nx):
     """(272, 260) has a 68 x 65 coarsest level: the per-factor polynomial
-    kernels; the others (up to the bench's 64 x 64, and a 30 x 66 one) fit the
-    single-workgroup LDS kernel."""
+    kernels; (120, 264) a 30 x 66 one: the single-workgroup kernel with the
+    residual in LDS; the others (up to the bench's 64 x 64, and a ragged
+    18 x 9 one) the single-workgroup kernel with one row strip per wave."""
     print(f"vcycle {nz}x{nx}", flush=True)
     med = medium(nz, nx, seed=nz + nx)
     H = setup(med)

@@ -136,6 +136,7 @@ def test_fused_resblock32(gpu, B, H, W_):
 FORCE_CASES = [
     # name, kind, stride, B, H, W, c1, c2, bcast2, cout, relu, resid
     ("s1_tiles", 0, 1, 2, 37, 50, 64, 0, False, 64, True, False),
+    ("s1_odd", 0, 1, 3, 33, 33, 64, 0, False, 64, True, False),    # 27 tiles: a tile pair spans two samples
     ("s1_n128", 0, 1, 1, 20, 18, 32, 0, False, 128, True, False),
     ("concat", 0, 1, 2, 18, 20, 32, 32, False, 32, True, False),
     ("ctx", 0, 1, 2, 17, 16, 32, 32, True, 64, True, False),
@@ -154,7 +155,8 @@ def test_every_convolution_kernel_against_oracle(gpu):
     """Each convolution kernel kind, pinned in turn, on every layer shape it
     applies to (stride 1 and 2, concatenated and broadcast context, residual,
     2-channel head, first layer, up-convolution, ragged 16 x 16 tiles) against
-    the oracle's direct convolution."""
+    the oracle's direct convolution, and on the stride-1 layers also the data
+    gradient, which runs the same kernels with flipped taps."""
     count = api.helm_conv_force(-1)
     assert count >= 9
     try:
@@ -177,6 +179,15 @@ def test_every_convolution_kernel_against_oracle(gpu):
                 resid = rnd((B, Ho, Wo, cout), 28) if use_resid else None
                 y = api.cnn_layer_forward(0, s, x1, Wt, b, x2=x2, bcast2=bc, resid=resid, relu=relu)
                 assert relerr(y, ref_conv(x1, x2, Wt, b, s, bc, relu, resid)) <= 1e-5
+                if s == 1 and c1 >= 32:
+                    # the data gradient: a flipped-kernel convolution accumulated into FP32
+                    g = rnd(y.shape, 29)
+                    gx1, gx2, _, _ = api.cnn_layer_backward(0, s, x1, Wt, y, g, x2=x2, bcast2=bc, relu=relu)
+                    gm = bf(g * (y > 0)) if relu else g
+                    x = x1 if x2 is None else np.concatenate([x1, np.broadcast_to(x2, x1.shape[:3] + x2.shape[3:])],
+                                                             axis=-1)
+                    rx, _, _ = U.conv3x3_backward(x, Wt, gm, s)
+                    assert relerr(gx1, rx[..., :c1]) <= 1e-5
     finally:
         api.helm_conv_force(-1)
     with pytest.raises(Exception):

@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import bf16_storage as B
-from helpers import f32, rand_c, relerr
+from helpers import f32, medium, rand_c, relerr
+from oracle import operator as op
 from oracle import unet as U
 from paper_2405_17696_amd import api, synth
 
@@ -28,15 +29,15 @@ def rnd(shape, seed, scale=1.0):
     return bf(scale * np.random.default_rng(seed).standard_normal(shape))
 
 
-@pytest.mark.parametrize("c2,bcast", [(0, False), (32, True)])
-def test_persistent_conv_many_tiles_per_block(gpu, c2, bcast):
+@pytest.mark.parametrize("ck,c1,c2,bcast,cout", [(CK_PERS, 32, 0, False, 32), (CK_PERS, 32, 32, True, 32)])
+def test_persistent_conv_many_tiles_per_block(gpu, ck, c1, c2, bcast, cout):
     Bn, H, W_ = 4, 256, 256
-    print("persistent conv multi-tile c2", c2, flush=True)
-    x1 = rnd((Bn, H, W_, 32), 31)
+    print("persistent conv multi-tile kernel", ck, "c1", c1, "c2", c2, "cout", cout, flush=True)
+    x1 = rnd((Bn, H, W_, c1), 31)
     x2 = rnd((1, H, W_, c2), 32) if c2 else None
-    Wt = rnd((32, 3, 3, 32 + c2), 33, scale=np.sqrt(2.0 / (9 * (32 + c2))))
-    b = rnd((32,), 34, 0.1)
-    api.helm_conv_force(CK_PERS)
+    Wt = rnd((cout, 3, 3, c1 + c2), 33, scale=np.sqrt(2.0 / (9 * (c1 + c2))))
+    b = rnd((cout,), 34, 0.1)
+    api.helm_conv_force(ck)
     try:
         y = api.cnn_layer_forward(0, 1, x1, Wt, b, x2=x2, bcast2=bcast, relu=True)
     finally:
@@ -155,3 +156,43 @@ def test_precond_apply_full_width_full_size(gpu):
         for s in range(2):
             assert relerr(outs[ck][s], ref[s]) <= 2e-2
 
+
+
+def test_forced_kernels_in_a_masked_solve(gpu):
+    """CNN-FGMRES(10) at 128 x 128 on right-hand sides that converge at
+    different iterations, so that the convolution kernels skip the finished
+    ones' tiles through the per-RHS flags, with the 64-channel layers on the
+    built-in choice and on the direct-load kernel: the kernels add the same
+    products in the same order, so iteration counts and solutions agree."""
+    n = 128
+    med = medium(n, n, seed=21)
+    H = api.helm_setup(torch.tensor(med.kappa2, dtype=torch.float32, device="cuda"),
+                       torch.tensor(med.gamma, dtype=torch.float32, device="cuda"), med.omega, med.h)
+    net = api.cnn_create(seed=1)
+    b = np.zeros((5, n, n), np.complex128)
+    b[0] = rand_c((n, n), 61)
+    b[1, n // 2, n // 2] = 1.0
+    b[2, 10, 17] = 1.0
+    b[3] = rand_c((n, n), 62)
+    b[4] = 0.5 * (b[0] + b[1])
+    bt = torch.tensor(b.astype(np.complex64), device="cuda")
+    api.helm_autotune(0)                                 # the built-in choice, not a timed one
+    res = {}
+    try:
+        for ck in (-1, CK_DL64):
+            print("masked solve, kernel", ck, flush=True)
+            api.helm_conv_force(ck)
+            x, it, rr, st, code = api.helm_solve(H, bt, tol=1e-6, precond="cnn_vu", maxit=600, net=net, restart=10)
+            assert code == 0 and np.all(st == 0)
+            res[ck] = (x.cpu().numpy(), it)
+            print("iterations", it, flush=True)
+    finally:
+        api.helm_conv_force(-1)
+        api.helm_autotune(1)                             # the library's default
+    x0, it0 = res[-1]
+    assert it0.max() > it0.min()                          # finished right-hand sides are masked for a while
+    coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
+    for ck, (x, it) in res.items():
+        assert np.all(np.abs(it - it0) <= 1)
+        assert relerr(x, x0) <= 1e-5
+        assert np.all(op.relres(coef, x, b, med.h, med.h) <= 1e-6)
