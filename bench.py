@@ -83,6 +83,9 @@ def parse():
                     help="time and count one launch in n of that kernel, chosen by a hash of the launch index "
                          "(event packets between all launches slow the timed solve by ~7%%)")
     ap.add_argument("--reorth", action="store_true", help="selective second Gram-Schmidt pass")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="CNN preconditioners: 2 applies the two halves of the batch on two streams, 1 the "
+                         "whole batch on one")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay comparison run")
     ap.add_argument("--sources", type=int, default=0, help="c3/c5: sources per system (0: the workload's)")
     ap.add_argument("--pretrain-steps", type=int, default=16000,
@@ -99,39 +102,54 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic():
+def measured_traffic(streams=2):
     """HBM bytes per launch of the convolution family from the committed counter
-    summary, or None when the kernels changed since the counters were taken."""
+    summary, or None when the kernels changed since the counters were taken or
+    the summary was taken with the preconditioner on another number of streams
+    (a launch then covers another number of right-hand sides)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "conv_family_hbm_traffic_256x256_32rhs.md")
     src = os.path.join(ROOT, "paper_2405_17696_amd", "csrc", "conv.hip")
+    keys = ("traffic_bytes_per_launch", "conv_source_sha256_16", "preconditioner_streams")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
-                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "conv_source_sha256_16"))
+                      and line.split(": ", 1)[0] in keys)
         cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if fields.get("conv_source_sha256_16") != cur:
+        if fields.get("conv_source_sha256_16") != cur or int(fields.get("preconditioner_streams", "1")) != streams:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def kernel_roofline(api_lib, name, every):
+def kernel_roofline(api_lib, name, every, by_steps=False):
     """Average event-timed duration and algorithmic work of the sampled launches
     (one in every launches of the family in the timed region, by a hash of the
-    launch index)."""
+    launch index; with by_steps every launch of one in every preconditioner
+    applications).  With by_steps (or every = 1) the achieved rate is the
+    family's work over the union of the sampled launches' intervals (its busy
+    wall time), which equals the per-launch figure when launches do not overlap
+    and stays a rate of the GPU when two streams run launches of the family
+    concurrently."""
     import ctypes as C
     n = C.c_int()
     ms = C.c_double()
     work = C.c_double()
     total = C.c_longlong()
+    busy = C.c_double()
     rc = api_lib.helm_ktimer_read(C.byref(n), C.byref(ms), C.byref(work))
     if rc != 0 or n.value == 0 or ms.value <= 0 or api_lib.helm_ktimer_count(C.byref(total)) != 0:
         return None
+    if api_lib.helm_ktimer_busy(C.byref(busy)) != 0 or busy.value <= 0:
+        return None
     avg_ms = ms.value / n.value
-    achieved = work.value / (ms.value * 1e-3) / 1e9
+    per_launch = work.value / (ms.value * 1e-3) / 1e9
+    achieved = work.value / (busy.value * 1e-3) / 1e9 if every == 1 or by_steps else per_launch
     return {"kernel": name, "launches": total.value, "sampled_launches": n.value, "sampled_every": every,
-            "avg_us": avg_ms * 1e3, "achieved": achieved, "work_per_launch": work.value / n.value}
+            "sampled_by": "preconditioner application" if by_steps else "launch",
+            "avg_us": avg_ms * 1e3, "achieved": achieved, "achieved_per_launch": per_launch,
+            "work_per_launch": work.value / n.value, "event_ms": ms.value, "busy_ms": busy.value,
+            "overlap": ms.value / busy.value}
 
 
 def _direct_worker(args):
@@ -327,27 +345,33 @@ def main_c2(a):
     if precond != "mg":
         net, training = get_net(api, a, k2, gam, med)
 
-    def step(pc, restart, use_graph):
+    def step(pc, restart, use_graph, streams):
         op = api.helm_setup(k2, gam, med.omega, med.h)
         out = api.helm_solve(op, b, x, tol=1e-6, precond=pc, maxit=a.maxit, net=net, reorth=a.reorth,
-                             use_graph=use_graph, restart=restart)
+                             use_graph=use_graph, restart=restart, streams=streams)
         op.close()
         return out
 
-    def run(pc, steps, warmup, restart, use_graph=False, timer=None):
+    def run(pc, steps, warmup, restart, use_graph=False, timer=None, streams=None):
+        streams = a.streams if streams is None else streams
         for _ in range(warmup):
-            step(pc, restart, use_graph)
+            step(pc, restart, use_graph, streams)
         torch.cuda.synchronize()
         if timer:
             _lib.check(lib.helm_ktimer_start(timer.encode()))
-            _lib.check(lib.helm_ktimer_sample(a.sample_every))
+            if timer == "k_conv":
+                # whole preconditioner applications, so that overlapping launches on two
+                # streams are timed together
+                _lib.check(lib.helm_ktimer_sample_steps(a.sample_every))
+            else:
+                _lib.check(lib.helm_ktimer_sample(a.sample_every))
         t0 = time.perf_counter()
         last = None
         for _ in range(steps):
-            last = step(pc, restart, use_graph)
+            last = step(pc, restart, use_graph, streams)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        roof = kernel_roofline(lib, timer, a.sample_every) if timer else None
+        roof = kernel_roofline(lib, timer, a.sample_every, by_steps=timer == "k_conv") if timer else None
         if timer:
             _lib.check(lib.helm_ktimer_start(None))
         return dt, last, roof
@@ -373,6 +397,10 @@ def main_c2(a):
             k = max(1, a.steps // 2)
             dt20, last20, _ = run(precond, k, 1, 20)
             compare[precond + "_restart20"] = {"rhs_per_s": nrhs * k / dt20, "iters_mean": float(last20[1].mean())}
+            other = 1 if a.streams == 2 else 2
+            dts, lasts, _ = run(precond, a.steps, 1, restart, streams=other)
+            compare[precond + ("_one_stream" if other == 1 else "_two_streams")] = {
+                "rhs_per_s": nrhs * a.steps / dts, "iters_mean": float(lasts[1].mean())}
             dtm, lastm, _ = run("mg", k, 1, 20)
             compare["mg"] = {"rhs_per_s": nrhs * k / dtm, "restart": 20, "iters_mean": float(lastm[1].mean())}
             compare["speedup_vs_mg"] = value / compare["mg"]["rhs_per_s"]
@@ -382,10 +410,12 @@ def main_c2(a):
         ach = roof["achieved"] / 1e3          # work counter holds flops: GFLOP/s -> TFLOP/s
         roofline = {"bound": "mfma", "kernel": roof["kernel"], "achieved": ach, "peak": BF16_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
-                    "traffic": measured_traffic() if precond == "cnn_vu" and restart == 10 else None,
+                    "traffic": measured_traffic(a.streams) if precond == "cnn_vu" and restart == 10 else None,
                     "avg_us": roof["avg_us"], "launches": roof["launches"],
                     "sampled_launches": roof["sampled_launches"], "sampled_every": roof["sampled_every"],
-                    "flops_per_launch": roof["work_per_launch"]}
+                    "sampled_by": roof["sampled_by"], "flops_per_launch": roof["work_per_launch"],
+                    "per_launch_frac": roof["achieved_per_launch"] / 1e3 / BF16_PEAK_TFLOPS,
+                    "busy_ms": roof["busy_ms"], "event_ms": roof["event_ms"], "overlap": roof["overlap"]}
     elif roof:
         roofline = {"bound": "hbm", "kernel": roof["kernel"], "achieved": roof["achieved"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": roof["achieved"] / HBM_PEAK_GBS, "traffic": None,
@@ -403,7 +433,8 @@ def main_c2(a):
            "dtype": ("bf16 network / " if precond != "mg" else "") + "c64 Krylov / c128 iterate / f64 residual",
            "data": "synthetic",
            "config": {"workload": "256x256 layered+GRF medium, 10 ppw, 32 surface sources, tol 1e-6",
-                      "precond": precond, "restart": restart, "global_batch": nrhs, "grid": [256, 256],
+                      "precond": precond, "restart": restart, "streams": a.streams if precond != "mg" else 1,
+                      "global_batch": nrhs, "grid": [256, 256],
                       "parallelism": "single GPU"},
            "compare": compare, "roofline": roofline, "cpu_baseline": cpu, "training": training,
            "autotuned_shapes": api.helm_autotune(-1)}

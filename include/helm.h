@@ -95,6 +95,11 @@ typedef struct {
     int use_graph;        /* 1: replay each restart cycle from a captured graph  */
     int reorth;           /* 1: second Gram-Schmidt pass when ||w|| drops by 0.7 */
     cnn_net_t net;        /* network for the CNN preconditioners                 */
+    int streams;          /* 2: the CNN preconditioners apply each operator's    */
+                          /* batch as two halves on two streams (the caller's    */
+                          /* and a library stream, joined by events, also under  */
+                          /* graph capture), so that the halves' kernels overlap;*/
+                          /* same results; 0 or 1: one stream                    */
 } helm_solve_opts;
 
 /*
@@ -431,10 +436,20 @@ int helm_conv_force(int kernel, int* kernel_count);
  */
 int helm_ktimer_start(const char* kernel);
 int helm_ktimer_sample(int every);
+/* Sample whole preconditioner applications of helm_solve instead: every
+ * launch of the family inside one in every applications (by the same hash of
+ * the application index) is timed and counted, on whichever stream it runs. */
+int helm_ktimer_sample_steps(int every);
 int helm_ktimer_read(int* launches, double* total_ms, double* total_work);
 /* All eager launches of the named family since helm_ktimer_start, sampled or
  * not (host output). */
 int helm_ktimer_count(long long* launches);
+/* Length of the union of the sampled launches' [start, end] intervals since
+ * helm_ktimer_start, in ms (host output; synchronises the device).  Without
+ * overlap it equals helm_ktimer_read's total; when the family's launches run
+ * concurrently on several streams, with every = 1 it is the wall time during
+ * which at least one of them ran. */
+int helm_ktimer_busy(double* busy_ms);
 
 const char* helm_last_error(void);
 /* Library version string. */

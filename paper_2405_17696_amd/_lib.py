@@ -35,7 +35,7 @@ class SetupOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("adjoint", C.c_int),
                 ("krylov_dtype", C.c_int), ("x0_given", C.c_int), ("use_graph", C.c_int),
-                ("reorth", C.c_int), ("net", C.c_void_p)]
+                ("reorth", C.c_int), ("net", C.c_void_p), ("streams", C.c_int)]
 
 
 class CnnArch(C.Structure):
@@ -123,8 +123,10 @@ SIGNATURES = {
     "cnn_layer_backward": (C.c_int, [C.c_int] * 9 + [C.c_void_p] * 4 + [C.c_int] + [C.c_void_p] * 5),
     "helm_ktimer_start": (C.c_int, [C.c_char_p]),
     "helm_ktimer_sample": (C.c_int, [C.c_int]),
+    "helm_ktimer_sample_steps": (C.c_int, [C.c_int]),
     "helm_ktimer_count": (C.c_int, [C.POINTER(C.c_longlong)]),
     "helm_ktimer_read": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "helm_ktimer_busy": (C.c_int, [C.POINTER(C.c_double)]),
     "helm_last_error": (C.c_char_p, []),
     "helm_version": (C.c_char_p, []),
 }

@@ -120,9 +120,10 @@ def helm_coarse_roots(op: HelmOp):
 def helm_solve(ops, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-6, rhs_op=None,
                precond: str = "mg", restart: int = 0, maxit: int = 300, adjoint: bool = False,
                krylov_dtype: str = "c64", x0_given: bool = False, use_graph: bool = False,
-               reorth: bool = False, net=None):
+               reorth: bool = False, net=None, streams: int = 1):
     """Solve H x = b for a batch.  ops: HelmOp or list; rhs complex64, x complex128.
-    Returns (x, iters, relres, status, code)."""
+    streams=2 applies a CNN preconditioner to the two halves of each operator's
+    batch on two streams.  Returns (x, iters, relres, status, code)."""
     import numpy as np
     lib = L.load()
     if isinstance(ops, HelmOp):
@@ -145,7 +146,7 @@ def helm_solve(ops, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float
     ro = (C.c_int * nrhs)(*rhs_op)
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, int(adjoint),
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, int(x0_given), int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     it = (C.c_int * nrhs)()
     rr = (C.c_double * nrhs)()
     stt = (C.c_int * nrhs)()

@@ -930,14 +930,16 @@ static int run_backward(cnn_net* net, Arena& A, Program& P, hipStream_t s) {
 
 // ------------------------------------------------------------------ arenas and encoder cache
 struct NetState {
-    std::map<std::tuple<int, int, int, int>, Arena*> arenas;  // (B, H, W, train)
+    std::map<std::tuple<int, int, int, int, int>, Arena*> arenas;  // (B, H, W, train, slot)
 };
 static std::map<const cnn_net*, NetState> g_state;
 static std::recursive_mutex g_cnn_mutex;
 
-static int get_arena(cnn_net* net, int B, int H, int W, bool train, Arena** out) {
+// slot tells apart arenas of the same shape that are in use at the same time
+// (the two halves of a batch applied on two streams).
+static int get_arena(cnn_net* net, int B, int H, int W, bool train, Arena** out, int slot = 0) {
     auto& ns = g_state[net];
-    auto key = std::make_tuple(B, H, W, (int)train);
+    auto key = std::make_tuple(B, H, W, (int)train, slot);
     auto it = ns.arenas.find(key);
     if (it != ns.arenas.end()) {
         *out = it->second;
@@ -1082,9 +1084,9 @@ struct ScaleBufs {
     double* sout = nullptr;
     int* bad = nullptr;
 };
-static int scale_bufs(int nrhs, ScaleBufs* out) {
-    static std::map<int, ScaleBufs> sbuf;
-    auto& sb = sbuf[nrhs];
+static int scale_bufs(int nrhs, ScaleBufs* out, int slot = 0) {
+    static std::map<std::pair<int, int>, ScaleBufs> sbuf;
+    auto& sb = sbuf[{nrhs, slot}];
     if (!sb.sin) {
         if (hipMalloc(&sb.sin, sizeof(double) * nrhs) != hipSuccess ||
             hipMalloc(&sb.sout, sizeof(double) * nrhs) != hipSuccess ||
@@ -1098,15 +1100,15 @@ static int scale_bufs(int nrhs, ScaleBufs* out) {
 // Everything a preconditioner application for nrhs right-hand sides of op
 // allocates or computes once (arena, encoder context, scale buffers), done
 // eagerly so that later applications can be captured into a graph.
-int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s) {
+int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s, int slot) {
     std::lock_guard<std::recursive_mutex> lk(g_cnn_mutex);
     int rc;
     if ((rc = check_grid(op))) return rc;
     Arena* A;
-    if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
+    if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A, slot))) return rc;
     if ((rc = ensure_encoded(net, op, A, s))) return rc;
     ScaleBufs sb;
-    return scale_bufs(nrhs, &sb);
+    return scale_bufs(nrhs, &sb, slot);
 }
 
 // e = M_net(r) for nrhs vectors.  Scales: s_in = sqrt(N) fscale (FGMRES basis
@@ -1115,14 +1117,14 @@ int cnn_prepare(cnn_net* net, const helm_op* op, int nrhs, hipStream_t s) {
 // value gets e = 0 instead (inside M_VU that leaves the V-cycle alone for it).
 template <typename T>
 static int apply_impl(cnn_net* net, const helm_op* op, const cx<T>* r, const double* fscale, int fstride, cx<T>* e,
-                      int nrhs, const RhsState* st, int rhs0, hipStream_t s, bool fallback = false) {
+                      int nrhs, const RhsState* st, int rhs0, hipStream_t s, bool fallback = false, int slot = 0) {
     int rc;
     if ((rc = check_grid(op))) return rc;
     Arena* A;
-    if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A))) return rc;
+    if ((rc = get_arena(net, nrhs, op->nz, op->nx, false, &A, slot))) return rc;
     if ((rc = ensure_encoded(net, op, A, s))) return rc;
     ScaleBufs sb;
-    if ((rc = scale_bufs(nrhs, &sb))) return rc;
+    if ((rc = scale_bufs(nrhs, &sb, slot))) return rc;
     const long N = op->n();
     const double sqrtN = std::sqrt((double)N), h2 = op->hx * op->hz;
     if (fscale) {
@@ -1151,12 +1153,13 @@ static int apply_impl(cnn_net* net, const helm_op* op, const cx<T>* r, const dou
 }
 
 int cnn_apply_masked(cnn_net* net, const helm_op* op, const void* r, const double* fscale, int fstride, void* e,
-                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s, bool fallback) {
+                     int nrhs, const RhsState* st, int rhs0, int wide, hipStream_t s, bool fallback, int slot) {
     std::lock_guard<std::recursive_mutex> lk(g_cnn_mutex);
     // fscale arrives offset to the current Arnoldi column; apply_impl adds rhs0*stride
     if (wide)
-        return apply_impl<double>(net, op, (const c128*)r, fscale, fstride, (c128*)e, nrhs, st, rhs0, s, fallback);
-    return apply_impl<float>(net, op, (const c64*)r, fscale, fstride, (c64*)e, nrhs, st, rhs0, s, fallback);
+        return apply_impl<double>(net, op, (const c128*)r, fscale, fstride, (c128*)e, nrhs, st, rhs0, s, fallback,
+                                  slot);
+    return apply_impl<float>(net, op, (const c64*)r, fscale, fstride, (c64*)e, nrhs, st, rhs0, s, fallback, slot);
 }
 
 // ------------------------------------------------------------------ training

@@ -38,6 +38,9 @@ struct KTimer {
     // after every launch of the named kernel: advance the launch count and decide
     // whether the next launch is sampled (every period-th launch is)
     void next(const char* name, hipStream_t s);
+    // at the start of each preconditioner application: when whole applications
+    // are sampled, decide whether this one's launches are
+    void step(hipStream_t s);
     unsigned long long* counter() const;
     bool capturing(hipStream_t s) const;
     void begin(hipStream_t s);

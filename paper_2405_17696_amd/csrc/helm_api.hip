@@ -111,6 +111,39 @@ static hipStream_t graph_stream() {
     return gs;
 }
 
+// Second stream of a preconditioner step split in two halves, with the events
+// that fork it from and join it back to the solve's stream.
+struct SplitStream {
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+static int split_stream(SplitStream** out) {
+    static SplitStream ss;
+    if (!ss.s2 && (hipStreamCreateWithFlags(&ss.s2, hipStreamNonBlocking) != hipSuccess ||
+                   hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+                   hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess)) {
+        ss.s2 = nullptr;
+        return fail(HELM_EHIP, "helm_solve: second stream");
+    }
+    *out = &ss;
+    return HELM_OK;
+}
+
+// The multigrid scratch of a batch, seen from its RHS `first` on.
+template <typename T>
+static MgWork<T> mg_from(const MgWork<T>& w, const helm_op* op, int first) {
+    MgWork<T> v = w;
+    for (int l = 1; l < op->nlev; ++l) {
+        v.f[l] += (long)first * op->lv[l].n();
+        v.e[l] += (long)first * op->lv[l].n();
+    }
+    const long nc = (long)first * op->lv[op->nlev - 1].n();
+    v.ra += nc;
+    v.rb += nc;
+    v.xw += nc;
+    return v;
+}
+
 template <typename T>
 static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const void* rhs, void* xv, int nrhs,
                       double tol, const helm_solve_opts& o, int* iters, double* relres, int* status, hipStream_t s,
@@ -155,6 +188,9 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     // multigrid scratch, reused group after group
     const bool use_mg = o.precond == HELM_PRECOND_MG || o.precond == HELM_PRECOND_CNN_VU;
     const bool use_cnn = o.precond == HELM_PRECOND_CNN || o.precond == HELM_PRECOND_CNN_VU;
+    const bool two_streams = use_cnn && o.streams == 2;
+    SplitStream* sp = nullptr;
+    if (two_streams && (rc = split_stream(&sp))) return rc;
     std::vector<MgWork<T>> mgw(groups.size());
     if (use_mg) {
         size_t need[MAX_LEVELS] = {0};
@@ -185,8 +221,15 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
         for (auto& gr : groups) maxg = std::max(maxg, (size_t)gr.n * ops[gr.op]->n());
         if ((rc = W.cnn_e0.ensure(sizeof(cx<T>) * maxg))) return rc;
         if ((rc = W.cnn_res.ensure(sizeof(cx<T>) * maxg))) return rc;
-        for (auto& gr : groups)
-            if ((rc = cnn_prepare(o.net, ops[gr.op], gr.n, s))) return rc;
+        for (auto& gr : groups) {
+            if (two_streams && gr.n >= 2) {
+                const int na = (gr.n + 1) / 2;
+                if ((rc = cnn_prepare(o.net, ops[gr.op], na, s, 0))) return rc;
+                if ((rc = cnn_prepare(o.net, ops[gr.op], gr.n - na, s, 1))) return rc;
+            } else if ((rc = cnn_prepare(o.net, ops[gr.op], gr.n, s))) {
+                return rc;
+            }
+        }
     }
 
     const c64* b = (const c64*)rhs;
@@ -240,6 +283,7 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     W.hst.resize(nrhs);
 
     auto precond = [&](int j) -> int {
+        ktimer().step(s);
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Grp& gr = groups[gi];
             const helm_op* op = ops[gr.op];
@@ -254,22 +298,58 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
                     r = launch_vcycle<T>(op, vj, a.vscale + j, m + 1, zj, nullptr, gr.n, a.st, gr.r0, mgw[gi], s);
                     break;
                 case HELM_PRECOND_CNN:
-                    r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)zj, gr.n, a.st,
-                                         gr.r0, sizeof(T) == 8, s);
+                case HELM_PRECOND_CNN_VU:
+                    if (two_streams && gr.n >= 2) {
+                        // the two halves of the group on two streams: each runs the network (and
+                        // for M_VU its residual and V-cycle) on its own workspaces and RHS range
+                        const int na = (gr.n + 1) / 2;
+                        r = HELM_OK;
+                        HELM_HIP(hipEventRecord(sp->fork, s));
+                        HELM_HIP(hipStreamWaitEvent(sp->s2, sp->fork, 0));
+                        for (int h = 0; h < 2 && !r; ++h) {
+                            const int first = h ? na : 0, nh = h ? gr.n - na : na;
+                            const long so = (long)first * op->n();
+                            hipStream_t sh = h ? sp->s2 : s;
+                            if (o.precond == HELM_PRECOND_CNN) {
+                                r = cnn_apply_masked(o.net, op, (const void*)(vj + so), a.vscale + j, m + 1,
+                                                     (void*)(zj + so), nh, a.st, gr.r0 + first, sizeof(T) == 8, sh,
+                                                     false, h);
+                                continue;
+                            }
+                            cx<T>* e0 = (cx<T>*)W.cnn_e0.p + so;
+                            cx<T>* res = (cx<T>*)W.cnn_res.p + so;
+                            GroupArgs<T> gh = ga[gi];
+                            gh.rhs0 += first;
+                            gh.off0 += so;
+                            MgWork<T> wh = mg_from(mgw[gi], op, first);
+                            r = cnn_apply_masked(o.net, op, (const void*)(vj + so), a.vscale + j, m + 1, (void*)e0,
+                                                 nh, a.st, gr.r0 + first, sizeof(T) == 8, sh, true, h);
+                            if (!r) r = launch_residual_vs_e0<T>(gh, nh, a, j, e0, res, sh);
+                            if (!r)
+                                r = launch_vcycle<T>(op, res, nullptr, 0, zj + so, e0, nh, a.st, gr.r0 + first, wh, sh);
+                        }
+                        HELM_HIP(hipEventRecord(sp->join, sp->s2));
+                        HELM_HIP(hipStreamWaitEvent(s, sp->join, 0));
+                        break;
+                    }
+                    if (o.precond == HELM_PRECOND_CNN) {
+                        r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)zj, gr.n, a.st,
+                                             gr.r0, sizeof(T) == 8, s);
+                        break;
+                    }
+                    {
+                        // a right-hand side whose network output is not finite gets
+                        // e0 = 0, i.e. M_VU = V_SL for that step
+                        cx<T>* e0 = (cx<T>*)W.cnn_e0.p;
+                        cx<T>* res = (cx<T>*)W.cnn_res.p;
+                        r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)e0, gr.n, a.st,
+                                             gr.r0, sizeof(T) == 8, s, true);
+                        if (r) return r;
+                        r = launch_residual_vs_e0<T>(ga[gi], gr.n, a, j, e0, res, s);
+                        if (r) return r;
+                        r = launch_vcycle<T>(op, res, nullptr, 0, zj, e0, gr.n, a.st, gr.r0, mgw[gi], s);
+                    }
                     break;
-                case HELM_PRECOND_CNN_VU: {
-                    // a right-hand side whose network output is not finite gets
-                    // e0 = 0, i.e. M_VU = V_SL for that step
-                    cx<T>* e0 = (cx<T>*)W.cnn_e0.p;
-                    cx<T>* res = (cx<T>*)W.cnn_res.p;
-                    r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)e0, gr.n, a.st,
-                                         gr.r0, sizeof(T) == 8, s, true);
-                    if (r) return r;
-                    r = launch_residual_vs_e0<T>(ga[gi], gr.n, a, j, e0, res, s);
-                    if (r) return r;
-                    r = launch_vcycle<T>(op, res, nullptr, 0, zj, e0, gr.n, a.st, gr.r0, mgw[gi], s);
-                    break;
-                }
                 default:
                     return fail(HELM_EINVAL, "unknown preconditioner %d", o.precond);
             }
@@ -560,6 +640,7 @@ int helm_solve(const helm_op_t* ops, int nops, const int* rhs_op, const void* rh
     if (o.restart <= 0) o.restart = cnn ? 10 : 20;
     if (o.restart > MAX_RESTART) return fail(HELM_EINVAL, "helm_solve: restart must be <= %d", MAX_RESTART);
     if (o.maxit <= 0) o.maxit = 300;
+    if (o.streams < 0 || o.streams > 2) return fail(HELM_EINVAL, "helm_solve: streams must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_mutex);
     hipStream_t s = (hipStream_t)stream;
     hipStream_t us = s;

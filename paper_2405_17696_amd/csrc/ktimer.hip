@@ -1,4 +1,5 @@
 // Per-kernel event timer and algorithmic-work counter (diagnostics).
+#include <algorithm>
 #include <string>
 #include <utility>
 #include <vector>
@@ -15,9 +16,12 @@ struct TimerState {
     size_t used = 0;
     unsigned long long* dcount = nullptr;
     hipEvent_t pending = nullptr;
+    hipEvent_t ref = nullptr;  // recorded at the start: the origin of the launch intervals
     int period = 1;            // every period-th launch is sampled
     long long launches = 0;    // launches of the named kernel since the start
     bool sample = true;        // whether the next launch is sampled
+    bool by_step = false;      // sample whole preconditioner applications, not single launches
+    long long steps = 0;       // preconditioner applications since the start
 };
 TimerState g_t;
 
@@ -62,7 +66,18 @@ void KTimer::end(hipStream_t s) {
 void KTimer::next(const char* name, hipStream_t s) {
     if (!named(name) || stream_capturing(s)) return;
     ++g_t.launches;
+    if (g_t.by_step) return;
     const unsigned h = (unsigned)g_t.launches * 2654435761u;
+    g_t.sample = g_t.period <= 1 || h < 0xFFFFFFFFu / (unsigned)g_t.period;
+}
+// The same hash over the index of the preconditioner application: every
+// launch of the family inside a sampled application is timed, on whichever
+// stream it runs, so that the union of their intervals is the family's busy
+// time in that application even when two streams overlap.
+void KTimer::step(hipStream_t s) {
+    if (!g_t.by_step || g_t.name.empty() || stream_capturing(s)) return;
+    ++g_t.steps;
+    const unsigned h = (unsigned)g_t.steps * 2654435761u;
     g_t.sample = g_t.period <= 1 || h < 0xFFFFFFFFu / (unsigned)g_t.period;
 }
 void KTimer::replayed() {}
@@ -83,7 +98,13 @@ extern "C" int helm_ktimer_start(const char* kernel) {
     g_t.used = 0;
     g_t.name = kernel ? kernel : "";
     g_t.launches = 0;
+    g_t.steps = 0;
     g_t.sample = true;
+    if (!g_t.ref && hipEventCreateWithFlags(&g_t.ref, hipEventDisableSystemFence) != hipSuccess) {
+        g_t.ref = nullptr;
+        return fail(HELM_EHIP, "helm_ktimer_start: event creation failed");
+    }
+    if (hipEventRecord(g_t.ref, nullptr) != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_start: event record failed");
     if (kernel) {
         const size_t bytes = sizeof(unsigned long long) * WORK_SLOTS * WORK_SLOT_STRIDE;
         if (!g_t.dcount && hipMalloc(&g_t.dcount, bytes) != hipSuccess)
@@ -97,6 +118,14 @@ extern "C" int helm_ktimer_start(const char* kernel) {
 extern "C" int helm_ktimer_sample(int every) {
     if (every < 1) return fail(HELM_EINVAL, "helm_ktimer_sample: every must be >= 1, got %d", every);
     g_t.period = every;
+    g_t.by_step = false;
+    return HELM_OK;
+}
+
+extern "C" int helm_ktimer_sample_steps(int every) {
+    if (every < 1) return fail(HELM_EINVAL, "helm_ktimer_sample_steps: every must be >= 1, got %d", every);
+    g_t.period = every;
+    g_t.by_step = true;
     return HELM_OK;
 }
 
@@ -126,5 +155,33 @@ extern "C" int helm_ktimer_read(int* launches, double* total_ms, double* total_w
     if (launches) *launches = (int)g_t.ev.size();
     if (total_ms) *total_ms = ms;
     if (total_work) *total_work = (double)w;
+    return HELM_OK;
+}
+
+extern "C" int helm_ktimer_busy(double* busy_ms) {
+    if (!busy_ms) return fail(HELM_EINVAL, "helm_ktimer_busy: NULL output");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_EHIP, "helm_ktimer_busy: device sync failed");
+    std::vector<std::pair<float, float>> iv;
+    iv.reserve(g_t.ev.size());
+    for (auto& p : g_t.ev) {
+        float a = 0, b = 0;
+        if (!g_t.ref || hipEventElapsedTime(&a, g_t.ref, p.first) != hipSuccess ||
+            hipEventElapsedTime(&b, g_t.ref, p.second) != hipSuccess)
+            return fail(HELM_EHIP, "helm_ktimer_busy: elapsed time failed");
+        iv.push_back({a, b});
+    }
+    std::sort(iv.begin(), iv.end());
+    double busy = 0, lo = 0, hi = -1;
+    for (auto& x : iv) {
+        if (x.first > hi) {
+            if (hi > lo) busy += hi - lo;
+            lo = x.first;
+            hi = x.second;
+        } else if (x.second > hi) {
+            hi = x.second;
+        }
+    }
+    if (hi > lo) busy += hi - lo;
+    *busy_ms = busy;
     return HELM_OK;
 }

@@ -33,19 +33,24 @@ def test_traffic_figure_follows_the_convolution_source(tmp_path, monkeypatch):
     bench = load_bench()
     text = open(os.path.join(ROOT, SUMMARY)).read()
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch: ", "conv_source_sha256_16: ")))
+                  if line.startswith(("traffic_bytes_per_launch: ", "conv_source_sha256_16: ",
+                                      "preconditioner_streams: ")))
     src = open(os.path.join(ROOT, CONV), "rb").read()
-    # the committed summary was taken on the current source
+    # the committed summary was taken on the current source, in the bench's default configuration
     assert fields["conv_source_sha256_16"] == hashlib.sha256(src).hexdigest()[:16]
-    assert bench.measured_traffic() == float(fields["traffic_bytes_per_launch"])
+    streams = int(fields["preconditioner_streams"])
+    assert streams == 2
+    assert bench.measured_traffic(streams) == float(fields["traffic_bytes_per_launch"])
+    # a launch of the other configuration covers another number of right-hand sides
+    assert bench.measured_traffic(3 - streams) is None
 
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2405_17696_amd" / "csrc").mkdir(parents=True)
     shutil.copy(os.path.join(ROOT, SUMMARY), tmp_path / SUMMARY)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / CONV).write_bytes(src)
-    assert bench.measured_traffic() == float(fields["traffic_bytes_per_launch"])
+    assert bench.measured_traffic(streams) == float(fields["traffic_bytes_per_launch"])
     (tmp_path / CONV).write_bytes(src + b"\n// changed\n")
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(streams) is None
     (tmp_path / CONV).unlink()
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(streams) is None

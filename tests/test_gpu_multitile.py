@@ -196,3 +196,44 @@ def test_forced_kernels_in_a_masked_solve(gpu):
         assert np.all(np.abs(it - it0) <= 1)
         assert relerr(x, x0) <= 1e-5
         assert np.all(op.relres(coef, x, b, med.h, med.h) <= 1e-6)
+
+
+@pytest.mark.parametrize("precond,use_graph", [("cnn_vu", False), ("cnn_vu", True), ("cnn", False)])
+def test_two_stream_preconditioner_matches_one_stream(gpu, precond, use_graph):
+    """streams=2 applies the network (and for M_VU its residual and V-cycle) to
+    the two halves of the batch (3 + 2 right-hand sides) on two streams, also
+    inside a captured restart cycle: every right-hand side sees the same
+    arithmetic as with one stream, so iterations and solutions agree."""
+    n = 128
+    med = medium(n, n, seed=23)
+    H = api.helm_setup(torch.tensor(med.kappa2, dtype=torch.float32, device="cuda"),
+                       torch.tensor(med.gamma, dtype=torch.float32, device="cuda"), med.omega, med.h)
+    net = api.cnn_create(seed=1)
+    b = np.zeros((5, n, n), np.complex128)
+    b[0] = rand_c((n, n), 71)
+    b[1, n // 3, n // 2] = 1.0
+    b[2] = rand_c((n, n), 72)
+    b[3, 5, 9] = 1.0
+    b[4] = 0.3 * b[0] + b[3]
+    bt = torch.tensor(b.astype(np.complex64), device="cuda")
+    maxit = 600 if precond == "cnn_vu" else 30
+    api.helm_autotune(0)
+    try:
+        out = {}
+        for streams in (1, 2):
+            print(precond, "graph", use_graph, "streams", streams, flush=True)
+            x, it, rr, st, code = api.helm_solve(H, bt, tol=1e-6, precond=precond, maxit=maxit, net=net, restart=10,
+                                                 use_graph=use_graph, streams=streams)
+            out[streams] = (x.cpu().numpy(), it, rr)
+            print("iterations", it, flush=True)
+    finally:
+        api.helm_autotune(1)
+    (x1, it1, rr1), (x2, it2, rr2) = out[1], out[2]
+    assert np.array_equal(it1, it2)
+    assert np.array_equal(rr1, rr2)
+    assert relerr(x2, x1) <= 1e-12
+    if precond == "cnn_vu":
+        coef = op.helmholtz_coef(med.kappa2, med.gamma, med.omega)
+        assert np.all(op.relres(coef, x2, b, med.h, med.h) <= 1e-6)
+    with pytest.raises(Exception):
+        api.helm_solve(H, bt, tol=1e-6, precond=precond, maxit=5, net=net, streams=3)
