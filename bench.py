@@ -544,7 +544,8 @@ def main_c3(a):
         while done < a.maxit:
             n_it = min(chunk, a.maxit - done)
             _, itc, rr, st, code = api.helm_solve(ops, b, x, tol=1e-6, rhs_op=rhs_op, precond=pc, maxit=n_it,
-                                                  restart=restart, use_graph=use_graph, net=net, x0_given=done > 0)
+                                                  restart=restart, use_graph=use_graph, net=net, x0_given=done > 0,
+                                                  streams=a.streams if pc != "mg" else 1)
             it += itc
             done += n_it
             print(f"c3 {'graph' if use_graph else 'eager'}: {done} iterations, {int((st == 0).sum())} converged, "
@@ -658,7 +659,7 @@ def main_c5(a):
     retrain_info = {"seconds": sec, "steps": len(hist), "dataset": dsz}
     log(f"c5 network retrained on the initial model in {sec:.1f} s")
     kws = {"mg": dict(precond="mg", maxit=a.maxit, restart=20),
-           "cnn_vu": dict(precond="cnn_vu", maxit=a.maxit, restart=a.restart, net=net)}
+           "cnn_vu": dict(precond="cnn_vu", maxit=a.maxit, restart=a.restart, net=net, streams=a.streams)}
     ops = [api.helm_setup(k0, gam, w, h) for w in d["omegas"]]
     out = {"pretraining": pre_info, "retraining_on_initial_model": retrain_info}
     grads = {}

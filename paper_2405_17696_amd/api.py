@@ -356,7 +356,7 @@ def cnn_layer_backward(kind, stride, x1, w, y, gout, x2=None, bcast2=False, relu
 # ---------------------------------------------------------------- FWI misfit and gradient
 def fwi_misfit_grad(ops, src_idx, rec_idx, dobs: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
                     restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
-                    reorth: bool = False, net=None, grad: torch.Tensor | None = None):
+                    reorth: bool = False, net=None, grad: torch.Tensor | None = None, streams: int = 1):
     """Misfit 1/2 sum |R u - d|^2 over frequencies (one op each) and sources, and its
     gradient w.r.t. the squared slowness.  src_idx / rec_idx: flat node indices;
     dobs complex64 [nfreq][nsrc][nrec] on the GPU.  Returns (misfit, grad float32
@@ -378,7 +378,7 @@ def fwi_misfit_grad(ops, src_idx, rec_idx, dobs: torch.Tensor, tol: float = 1e-6
     handles = (C.c_void_p * nf)(*[o.handle for o in ops])
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     phi = C.c_double()
     its = (C.c_int * (2 * nf * ns))()
     code = lib.fwi_misfit_grad(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(dobs),
@@ -389,7 +389,7 @@ def fwi_misfit_grad(ops, src_idx, rec_idx, dobs: torch.Tensor, tol: float = 1e-6
 
 def fwi_misfit_grad_encoded(ops, src_idx, X, rec_idx, dobs: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
                             restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
-                            reorth: bool = False, net=None, grad: torch.Tensor | None = None):
+                            reorth: bool = False, net=None, grad: torch.Tensor | None = None, streams: int = 1):
     """Simultaneous-source misfit 1/2 (1/p) sum |R H^{-1} G x_i - D x_i|^2 and its
     gradient (Sec. 3.2); X real [nsrc][p] (host), dobs the unencoded data,
     complex64 [nfreq][nsrc][nrec] on the GPU.  Returns (misfit, grad float32
@@ -415,7 +415,7 @@ def fwi_misfit_grad_encoded(ops, src_idx, X, rec_idx, dobs: torch.Tensor, tol: f
     handles = (C.c_void_p * nf)(*[o.handle for o in ops])
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     phi = C.c_double()
     its = (C.c_int * (2 * nf * p))()
     code = lib.fwi_misfit_grad_encoded(handles, nf, (C.c_int * ns)(*src), ns,
@@ -426,7 +426,7 @@ def fwi_misfit_grad_encoded(ops, src_idx, X, rec_idx, dobs: torch.Tensor, tol: f
 
 
 def _fwi_lin(name, ops, src_idx, rec_idx, x: torch.Tensor, tol, precond, restart, maxit, krylov_dtype, use_graph,
-             reorth, net):
+             reorth, net, streams=1):
     """Shared marshalling of fwi_born / fwi_born_adjoint / fwi_gn_hessvec."""
     import numpy as np
     lib = L.load()
@@ -448,7 +448,7 @@ def _fwi_lin(name, ops, src_idx, rec_idx, x: torch.Tensor, tol, precond, restart
     handles = (C.c_void_p * nf)(*[o.handle for o in ops])
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     nb = 3 if name == "fwi_gn_hessvec" else 2
     its = (C.c_int * (nb * nf * ns))()
     code = getattr(lib, name)(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(x), float(tol),
@@ -458,27 +458,28 @@ def _fwi_lin(name, ops, src_idx, rec_idx, x: torch.Tensor, tol, precond, restart
 
 
 def fwi_born(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, precond: str = "mg", restart: int = 0,
-             maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None):
+             maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None,
+             streams: int = 1):
     """J dm: linearised data, complex64 [nfreq][nsrc][nrec].  Returns (jdm, iters [2][nfreq][nsrc], code)."""
     return _fwi_lin("fwi_born", ops, src_idx, rec_idx, dm, tol, precond, restart, maxit, krylov_dtype, use_graph,
-                    reorth, net)
+                    reorth, net, streams)
 
 
 def fwi_born_adjoint(ops, src_idx, rec_idx, dd: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
                      restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
-                     reorth: bool = False, net=None):
+                     reorth: bool = False, net=None, streams: int = 1):
     """Re(J^H dd), float32 [nz][nx].  Returns (out, iters [2][nfreq][nsrc], code)."""
     return _fwi_lin("fwi_born_adjoint", ops, src_idx, rec_idx, dd, tol, precond, restart, maxit, krylov_dtype,
-                    use_graph, reorth, net)
+                    use_graph, reorth, net, streams)
 
 
 def fwi_gn_hessvec(ops, src_idx, rec_idx, dm: torch.Tensor, tol: float = 1e-6, precond: str = "mg",
                    restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64", use_graph: bool = False,
-                   reorth: bool = False, net=None):
+                   reorth: bool = False, net=None, streams: int = 1):
     """Re(J^H J dm), the Gauss-Newton Hessian applied to dm, float32 [nz][nx].
     Returns (out, iters [3][nfreq][nsrc], code)."""
     return _fwi_lin("fwi_gn_hessvec", ops, src_idx, rec_idx, dm, tol, precond, restart, maxit, krylov_dtype,
-                    use_graph, reorth, net)
+                    use_graph, reorth, net, streams)
 
 
 def _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref):
@@ -496,7 +497,7 @@ def _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref):
 def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_iters: int = 10, tol: float = 1e-6,
               tol_sens: float = 0.0, reg: str = "none", alpha: float = 0.0, m_ref: torch.Tensor | None = None,
               precond: str = "mg", restart: int = 0, maxit: int = 300, krylov_dtype: str = "c64",
-              use_graph: bool = False, reorth: bool = False, net=None):
+              use_graph: bool = False, reorth: bool = False, net=None, streams: int = 1):
     """cg_iters CG steps on (Re(J^H J) + alpha nabla^2 R + damping I) x = b from
     x = 0; b float32 [nz][nx] on the GPU; the point-source fields at tol, the
     Born and adjoint solves at tol_sens (<= 0: tol).  Returns (x float32
@@ -516,7 +517,7 @@ def fwi_gn_cg(ops, src_idx, rec_idx, b: torch.Tensor, damping: float = 0.0, cg_i
     g = _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref)
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     norms = (C.c_double * (cg_iters + 1))()
     its = (C.c_int * max(1, 2 * cg_iters * nf * ns))()
     code = lib.fwi_gn_cg(handles, nf, (C.c_int * ns)(*src), ns, (C.c_int * nr)(*rec), nr, _ptr(b), C.byref(g),
@@ -530,7 +531,7 @@ def fwi_gn_step(ops, src_idx, rec_idx, dobs: torch.Tensor, m: torch.Tensor, damp
                 mu: float = 1.0, tol: float = 1e-6, tol_sens: float = 0.0, reg: str = "none", alpha: float = 0.0,
                 m_ref: torch.Tensor | None = None, precond: str = "mg", restart: int = 0, maxit: int = 300,
                 krylov_dtype: str = "c64", use_graph: bool = False, reorth: bool = False, net=None,
-                m_new: torch.Tensor | None = None):
+                m_new: torch.Tensor | None = None, streams: int = 1):
     """One Gauss-Newton step m + mu dm on Phi + alpha R, dm from CG on
     (Re(J^H J) + alpha nabla^2 R + damping I) dm = -grad; ops must be set up
     with m.  Returns a dict: m_new, misfit (data misfit at m), reg (R(m)),
@@ -554,7 +555,7 @@ def fwi_gn_step(ops, src_idx, rec_idx, dobs: torch.Tensor, m: torch.Tensor, damp
     g = _gn_opts(damping, cg_iters, tol_sens, reg, alpha, m_ref)
     o = L.SolveOpts(L.PRECOND[precond], restart, maxit, 0,
                     L.HELM_C64 if krylov_dtype == "c64" else L.HELM_C128, 0, int(use_graph),
-                    int(reorth), C.c_void_p(net.handle.value if net is not None else None))
+                    int(reorth), C.c_void_p(net.handle.value if net is not None else None), int(streams))
     phi = C.c_double()
     rv = C.c_double()
     norms = (C.c_double * (cg_iters + 1))()

@@ -89,6 +89,9 @@ def test_autograd_function(gpu):
 
 
 def test_gradient_with_cnn_preconditioner(gpu):
+    """The CNN-FGMRES path against the oracle's gradient; with the network on
+    two streams (one source per stream) the forward and adjoint solves, and so
+    misfit, gradient and iteration counts, are those of one stream."""
     k2, gamma, omegas, h, src, rec, dobs = problem(nz=64, nx=64, nsrc=2, nrec=5, freqs=(10.0,))
     dobs = dobs.astype(np.complex64).astype(np.complex128)
     net = api.cnn_create(seed=3)
@@ -98,6 +101,11 @@ def test_gradient_with_cnn_preconditioner(gpu):
     assert code == 0
     assert abs(phi - phi_o) <= 1e-2 * phi_o
     assert relerr(g, g_o) <= 1e-3
+    phi2, g2, its2, code2 = gpu_call(k2, gamma, omegas, h, src, rec, dobs, tol=1e-6, precond="cnn_vu", net=net,
+                                     restart=10, streams=2)
+    assert code2 == 0 and np.array_equal(its2, its)
+    assert phi2 == pytest.approx(phi, rel=1e-12)
+    assert relerr(g2, g) <= 1e-12
 
 
 def test_zero_residual(gpu):
