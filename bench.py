@@ -125,8 +125,7 @@ def measured_traffic(streams=2):
 def kernel_roofline(api_lib, name, every, by_steps=False):
     """Average event-timed duration and algorithmic work of the sampled launches
     (one in every launches of the family in the timed region, by a hash of the
-    launch index; with by_steps every launch of one in every preconditioner
-    applications).  With by_steps (or every = 1) the achieved rate is the
+    launch index; with by_steps every launch of one in every restart cycles).  With by_steps (or every = 1) the achieved rate is the
     family's work over the union of the sampled launches' intervals (its busy
     wall time), which equals the per-launch figure when launches do not overlap
     and stays a rate of the GPU when two streams run launches of the family
@@ -146,7 +145,7 @@ def kernel_roofline(api_lib, name, every, by_steps=False):
     per_launch = work.value / (ms.value * 1e-3) / 1e9
     achieved = work.value / (busy.value * 1e-3) / 1e9 if every == 1 or by_steps else per_launch
     return {"kernel": name, "launches": total.value, "sampled_launches": n.value, "sampled_every": every,
-            "sampled_by": "preconditioner application" if by_steps else "launch",
+            "sampled_by": "restart cycle" if by_steps else "launch",
             "avg_us": avg_ms * 1e3, "achieved": achieved, "achieved_per_launch": per_launch,
             "work_per_launch": work.value / n.value, "event_ms": ms.value, "busy_ms": busy.value,
             "overlap": ms.value / busy.value}
@@ -360,8 +359,8 @@ def main_c2(a):
         if timer:
             _lib.check(lib.helm_ktimer_start(timer.encode()))
             if timer == "k_conv":
-                # whole preconditioner applications, so that overlapping launches on two
-                # streams are timed together
+                # whole restart cycles, so that overlapping launches on two streams are
+                # timed together
                 _lib.check(lib.helm_ktimer_sample_steps(a.sample_every))
             else:
                 _lib.check(lib.helm_ktimer_sample(a.sample_every))

@@ -436,9 +436,9 @@ int helm_conv_force(int kernel, int* kernel_count);
  */
 int helm_ktimer_start(const char* kernel);
 int helm_ktimer_sample(int every);
-/* Sample whole preconditioner applications of helm_solve instead: every
- * launch of the family inside one in every applications (by the same hash of
- * the application index) is timed and counted, on whichever stream it runs. */
+/* Sample whole restart cycles of helm_solve instead: every launch of the
+ * family inside one in every cycles (by the same hash of the cycle index) is
+ * timed and counted, on whichever stream it runs. */
 int helm_ktimer_sample_steps(int every);
 int helm_ktimer_read(int* launches, double* total_ms, double* total_work);
 /* All eager launches of the named family since helm_ktimer_start, sampled or

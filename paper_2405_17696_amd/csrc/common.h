@@ -38,8 +38,8 @@ struct KTimer {
     // after every launch of the named kernel: advance the launch count and decide
     // whether the next launch is sampled (every period-th launch is)
     void next(const char* name, hipStream_t s);
-    // at the start of each preconditioner application: when whole applications
-    // are sampled, decide whether this one's launches are
+    // at the start of each restart cycle of helm_solve: when whole cycles are
+    // sampled, decide whether this one's launches are
     void step(hipStream_t s);
     unsigned long long* counter() const;
     bool capturing(hipStream_t s) const;

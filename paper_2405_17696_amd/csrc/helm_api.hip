@@ -282,8 +282,33 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     }
     W.hst.resize(nrhs);
 
+    // A CNN preconditioner on RHS first .. first + nh - 1 of group gi (its network
+    // workspaces: slot), on stream sh.  M_VU: e0 = M_net(v), then the V-cycle of
+    // the residual v - H e0 added to e0; a right-hand side whose network output is
+    // not finite gets e0 = 0, i.e. M_VU = V_SL for that step.
+    auto precond_part = [&](size_t gi, int first, int nh, int j, hipStream_t sh, int slot) -> int {
+        const Grp& gr = groups[gi];
+        const helm_op* op = ops[gr.op];
+        const long so = (long)first * op->n();
+        cx<T>* vj = a.V + (long)j * Ntot + gr.off0 + so;
+        cx<T>* zj = a.Z + (long)j * Ntot + gr.off0 + so;
+        if (o.precond == HELM_PRECOND_CNN)
+            return cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)zj, nh, a.st,
+                                    gr.r0 + first, sizeof(T) == 8, sh, false, slot);
+        cx<T>* e0 = (cx<T>*)W.cnn_e0.p + so;
+        cx<T>* res = (cx<T>*)W.cnn_res.p + so;
+        GroupArgs<T> gh = ga[gi];
+        gh.rhs0 += first;
+        gh.off0 += so;
+        MgWork<T> wh = mg_from(mgw[gi], op, first);
+        int r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)e0, nh, a.st, gr.r0 + first,
+                                 sizeof(T) == 8, sh, true, slot);
+        if (!r) r = launch_residual_vs_e0<T>(gh, nh, a, j, e0, res, sh);
+        if (!r) r = launch_vcycle<T>(op, res, nullptr, 0, zj, e0, nh, a.st, gr.r0 + first, wh, sh);
+        return r;
+    };
+
     auto precond = [&](int j) -> int {
-        ktimer().step(s);
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Grp& gr = groups[gi];
             const helm_op* op = ops[gr.op];
@@ -300,54 +325,18 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
                 case HELM_PRECOND_CNN:
                 case HELM_PRECOND_CNN_VU:
                     if (two_streams && gr.n >= 2) {
-                        // the two halves of the group on two streams: each runs the network (and
-                        // for M_VU its residual and V-cycle) on its own workspaces and RHS range
+                        // the two halves of the group on two streams, each on its own workspaces,
+                        // joined before the Arnoldi step (and before the next group, which reuses
+                        // the scratch)
                         const int na = (gr.n + 1) / 2;
-                        r = HELM_OK;
                         HELM_HIP(hipEventRecord(sp->fork, s));
                         HELM_HIP(hipStreamWaitEvent(sp->s2, sp->fork, 0));
-                        for (int h = 0; h < 2 && !r; ++h) {
-                            const int first = h ? na : 0, nh = h ? gr.n - na : na;
-                            const long so = (long)first * op->n();
-                            hipStream_t sh = h ? sp->s2 : s;
-                            if (o.precond == HELM_PRECOND_CNN) {
-                                r = cnn_apply_masked(o.net, op, (const void*)(vj + so), a.vscale + j, m + 1,
-                                                     (void*)(zj + so), nh, a.st, gr.r0 + first, sizeof(T) == 8, sh,
-                                                     false, h);
-                                continue;
-                            }
-                            cx<T>* e0 = (cx<T>*)W.cnn_e0.p + so;
-                            cx<T>* res = (cx<T>*)W.cnn_res.p + so;
-                            GroupArgs<T> gh = ga[gi];
-                            gh.rhs0 += first;
-                            gh.off0 += so;
-                            MgWork<T> wh = mg_from(mgw[gi], op, first);
-                            r = cnn_apply_masked(o.net, op, (const void*)(vj + so), a.vscale + j, m + 1, (void*)e0,
-                                                 nh, a.st, gr.r0 + first, sizeof(T) == 8, sh, true, h);
-                            if (!r) r = launch_residual_vs_e0<T>(gh, nh, a, j, e0, res, sh);
-                            if (!r)
-                                r = launch_vcycle<T>(op, res, nullptr, 0, zj + so, e0, nh, a.st, gr.r0 + first, wh, sh);
-                        }
+                        r = precond_part(gi, 0, na, j, s, 0);
+                        if (!r) r = precond_part(gi, na, gr.n - na, j, sp->s2, 1);
                         HELM_HIP(hipEventRecord(sp->join, sp->s2));
                         HELM_HIP(hipStreamWaitEvent(s, sp->join, 0));
-                        break;
-                    }
-                    if (o.precond == HELM_PRECOND_CNN) {
-                        r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)zj, gr.n, a.st,
-                                             gr.r0, sizeof(T) == 8, s);
-                        break;
-                    }
-                    {
-                        // a right-hand side whose network output is not finite gets
-                        // e0 = 0, i.e. M_VU = V_SL for that step
-                        cx<T>* e0 = (cx<T>*)W.cnn_e0.p;
-                        cx<T>* res = (cx<T>*)W.cnn_res.p;
-                        r = cnn_apply_masked(o.net, op, (const void*)vj, a.vscale + j, m + 1, (void*)e0, gr.n, a.st,
-                                             gr.r0, sizeof(T) == 8, s, true);
-                        if (r) return r;
-                        r = launch_residual_vs_e0<T>(ga[gi], gr.n, a, j, e0, res, s);
-                        if (r) return r;
-                        r = launch_vcycle<T>(op, res, nullptr, 0, zj, e0, gr.n, a.st, gr.r0, mgw[gi], s);
+                    } else {
+                        r = precond_part(gi, 0, gr.n, j, s, 0);
                     }
                     break;
                 default:
@@ -362,7 +351,8 @@ static int solve_impl(const helm_op_t* ops, int nops, const int* rhs_op, const v
     // by the true residual that opens the next cycle.  Eager, or replayed
     // from a graph captured on the first cycle.
     auto cycle_body = [&]() -> int {
-        int r;
+        int r = HELM_OK;
+        ktimer().step(s);
         for (int j = 0; j < m; ++j) {
             if ((r = precond(j))) return r;
             for (size_t gi = 0; gi < groups.size(); ++gi)

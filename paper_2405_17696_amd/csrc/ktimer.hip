@@ -20,8 +20,8 @@ struct TimerState {
     int period = 1;            // every period-th launch is sampled
     long long launches = 0;    // launches of the named kernel since the start
     bool sample = true;        // whether the next launch is sampled
-    bool by_step = false;      // sample whole preconditioner applications, not single launches
-    long long steps = 0;       // preconditioner applications since the start
+    bool by_step = false;      // sample whole restart cycles, not single launches
+    long long steps = 0;       // restart cycles since the start
 };
 TimerState g_t;
 
@@ -70,10 +70,10 @@ void KTimer::next(const char* name, hipStream_t s) {
     const unsigned h = (unsigned)g_t.launches * 2654435761u;
     g_t.sample = g_t.period <= 1 || h < 0xFFFFFFFFu / (unsigned)g_t.period;
 }
-// The same hash over the index of the preconditioner application: every
-// launch of the family inside a sampled application is timed, on whichever
-// stream it runs, so that the union of their intervals is the family's busy
-// time in that application even when two streams overlap.
+// The same hash over the index of the restart cycle: every launch of the
+// family inside a sampled cycle is timed, on whichever stream it runs, so that
+// the union of their intervals is the family's busy time in that cycle even
+// when two streams overlap (they join at the end of every cycle).
 void KTimer::step(hipStream_t s) {
     if (!g_t.by_step || g_t.name.empty() || stream_capturing(s)) return;
     ++g_t.steps;
