@@ -99,7 +99,8 @@ typedef struct {
                           /* batch as two halves on two streams (the caller's    */
                           /* and a library stream, joined by events, also under  */
                           /* graph capture), so that the halves' kernels overlap;*/
-                          /* same results; 0 or 1: one stream                    */
+                          /* with the same convolution kernels, the same results;*/
+                          /* 0 or 1: one stream                                  */
 } helm_solve_opts;
 
 /*
