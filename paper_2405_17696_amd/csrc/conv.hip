@@ -418,6 +418,205 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* p, unsigned 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
 }
 
+// ------------------------------------------------------------------ implicit GEMM, deeper prefetch
+// The implicit GEMM above keeps one 32-deep chunk of A and B in flight.  At the
+// stride-2 layers a chunk holds only 4 to 8 MFMAs per wave and every chunk waits
+// for its own loads, so a block costs about one load latency per chunk.  This
+// form keeps GPF_D chunks in flight in registers.  It serves forward 3 x 3
+// convolutions (any stride) whose sources have multiples of 32 channels: a chunk
+// then lies within one tap and one source, so tap, source and channel offset are
+// the same for the whole chunk, and each thread decodes its pixels once.  Every
+// load is a raw buffer load, a fixed number per chunk (a read outside the image,
+// past M or past N gets an offset past the buffer, which reads zeros), so the
+// wait before a chunk's LDS store covers that chunk's loads only.  The sums run
+// over K in the order of k_gemm, so the two give the same results.
+constexpr int GPF_D = 3;                   // chunks in flight: divides 9, 18 and 36 (C = 32, 64, 128)
+constexpr unsigned GPF_OOR = 0x80000000u;  // an offset no descriptor here reaches (byte counts < 2^31)
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void k_gemm_pf(GemmArgs a, unsigned long long* wc) {
+    constexpr int WTM = BM / WGM / 16, WTN = BN / WGN / 16;
+    constexpr int ASEG = BM * KC / 8, BSEG = BN * KC / 8;
+    constexpr int APT = (ASEG + 255) / 256, BPT = (BSEG + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 smem[2 * (BM + BN) * LDS_K];
+    bf16 (*As)[BM][LDS_K] = reinterpret_cast<bf16 (*)[BM][LDS_K]>(smem);
+    bf16 (*Bs)[BN][LDS_K] = reinterpret_cast<bf16 (*)[BN][LDS_K]>(smem + 2 * BM * LDS_K);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const long m0 = (long)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int nchunk = a.K / KC;   // a multiple of GPF_D (checked by the launcher)
+    if (a.st && ((long)a.Ho * a.Wo) % BM == 0) {
+        // a tile never straddles two samples when Ho*Wo is a multiple of BM
+        const int b = (int)(m0 / ((long)a.Ho * a.Wo));
+        const RhsState& S = a.st[a.rhs0 + b];
+        if (!S.active || S.cycdone) return;
+    }
+    if (wc && tid == 0) {
+        long mr = a.M - m0 < BM ? a.M - m0 : BM;
+        int nr = a.N - n0 < BN ? a.N - n0 : BN;
+        work_atomic(wc, (unsigned long long)(2ull * mr * nr * (unsigned long long)a.kvalid));
+    }
+    __shared__ __attribute__((aligned(16))) float bias_s[BN];
+    if (tid < BN) bias_s[tid] = a.bias && n0 + tid < a.N ? a.bias[n0 + tid] : 0.f;
+
+    // per thread: the pixel of each A segment (source element offsets of its sample,
+    // top-left input position of its 3 x 3 window) and the weight row of each B segment
+    int ay[APT], ax[APT];
+    unsigned ab1[APT], ab2[APT], asub[APT];
+    bool arow[APT];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const int sg = tid + q * 256, row = sg >> 2;
+        const long m = m0 + row;
+        arow[q] = sg < ASEG && m < a.M;
+        const Pix p = pix_of(arow[q] ? m : 0, a.Ho, a.Wo);
+        ay[q] = p.y * a.stride - 1;
+        ax[q] = p.x * a.stride - 1;
+        ab1[q] = (unsigned)((long)p.b * a.abs1);
+        ab2[q] = (unsigned)((long)p.b * a.abs2);
+        asub[q] = (unsigned)((sg & 3) * 8);
+    }
+    unsigned boff[BPT];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        const int sg = tid + q * 256, n = n0 + (sg >> 2);
+        boff[q] = sg < BSEG && n < a.N ? (unsigned)(((long)n * a.K + (sg & 3) * 8) * 2) : GPF_OOR;
+    }
+    const long s1n = a.abs1 ? (long)a.B * a.abs1 : (long)a.Hi * a.Wi * a.c1;
+    const long s2n = a.c2 ? (a.abs2 ? (long)a.B * a.abs2 : (long)a.Hi * a.Wi * a.c2) : 0;
+    const __amdgpu_buffer_rsrc_t rs1 = brsrc(a.a1, (unsigned)(s1n * 2));
+    const __amdgpu_buffer_rsrc_t rs2 = brsrc(a.c2 ? a.a2 : a.a1, (unsigned)((a.c2 ? s2n : s1n) * 2));
+    const __amdgpu_buffer_rsrc_t rsw = brsrc(a.w, (unsigned)((long)a.N * a.K * 2));
+    const int C = a.c1 + a.c2;
+
+    // loads of chunk kc (none past the last chunk: every offset out of range)
+    struct Set {
+        bf16x8 a[APT], b[BPT];
+    };
+    auto issue = [&](int kc) -> Set {
+        Set r;
+        const bool live = kc < nchunk;
+        const int k0 = kc * KC;
+        const int tap = k0 / C, c0 = k0 - tap * C;
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const bool src2 = c0 >= a.c1;
+        const int cs = src2 ? a.c2 : a.c1, cc = src2 ? c0 - a.c1 : c0;
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            const int yi = ay[q] + ky, xi = ax[q] + kx;
+            const bool ok = live && arow[q] && (unsigned)yi < (unsigned)a.Hi && (unsigned)xi < (unsigned)a.Wi;
+            const unsigned off =
+                ok ? ((src2 ? ab2[q] : ab1[q]) + (unsigned)((yi * a.Wi + xi) * cs + cc) + asub[q]) * 2u : GPF_OOR;
+            r.a[q] = bload8(src2 ? rs2 : rs1, off);
+        }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q)
+            r.b[q] = bload8(rsw, live && boff[q] != GPF_OOR ? boff[q] + (unsigned)k0 * 2u : GPF_OOR);
+        return r;
+    };
+    auto store = [&](int buf, const Set& r) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg < ASEG) *reinterpret_cast<bf16x8*>(&As[buf][sg >> 2][(sg & 3) * 8]) = r.a[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int sg = tid + q * 256;
+            if (sg < BSEG) *reinterpret_cast<bf16x8*>(&Bs[buf][sg >> 2][(sg & 3) * 8]) = r.b[q];
+        }
+    };
+    f32x4 acc[WTM][WTN];
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    auto mma = [&](int buf) {
+        bf16x8 fa[WTM], fb[WTN];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+            fa[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * (BM / WGM) + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * (BN / WGN) + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+            for (int j = 0; j < WTN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j], fa[i], acc[i][j], 0, 0, 0);
+    };
+
+    // chunk c is multiplied from LDS buffer c & 1; three register sets hold the next
+    // chunks, each refilled GPF_D chunks ahead as soon as its chunk is in LDS
+    Set r0 = issue(0), r1 = issue(1), r2 = issue(2);
+    store(0, r0);
+    __syncthreads();
+    for (int kc = 0; kc < nchunk; kc += GPF_D) {
+        r0 = issue(kc + 3);
+        mma(kc & 1);
+        store((kc + 1) & 1, r1);
+        __syncthreads();
+        r1 = issue(kc + 4);
+        mma((kc + 1) & 1);
+        store(kc & 1, r2);
+        __syncthreads();
+        r2 = issue(kc + 5);
+        mma(kc & 1);
+        if (kc + 3 < nchunk) {
+            store((kc + 1) & 1, r0);
+            __syncthreads();
+        }
+    }
+
+    // epilogue through LDS, as in k_gemm's forward path: each lane finishes its four
+    // channels of one pixel into an LDS copy of the tile, then whole 16-byte rows
+    constexpr int SP = BN + 8;
+    static_assert(sizeof(smem) >= (size_t)BM * SP * sizeof(bf16), "epilogue tile");
+    bf16* ot = smem;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < WTM; ++i) {
+        const int ml = wm * (BM / WGM) + i * 16 + (lane & 15);
+        const long m = m0 + ml;
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+            const int nl = wn * (BN / WGN) + j * 16 + (lane >> 4) * 4, n = n0 + nl;
+            f32x4 v = acc[i][j];
+            if (m < a.M && n < a.N) {
+                const long pm = m % ((long)a.Ho * a.Wo);
+                const float4 bb =
+                    a.bmap ? bmap4(a.bmap + pm * a.N + n) : *reinterpret_cast<const float4*>(bias_s + nl);
+                v[0] += bb.x;
+                v[1] += bb.y;
+                v[2] += bb.z;
+                v[3] += bb.w;
+                if (a.resid) {
+                    const bf16x4g r = *reinterpret_cast<const bf16x4g*>(a.resid + m * a.N + n);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += (float)r[e];
+                }
+                if (a.relu)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                if (a.outf) *reinterpret_cast<f32x4*>(a.outf + m * a.N + n) = v;   // FP32 copy (layer tests)
+            }
+            bf16x4g o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+            *reinterpret_cast<bf16x4g*>(ot + ml * SP + nl) = o;
+        }
+    }
+    __syncthreads();
+    constexpr int CPR = BN / 8;
+    for (int k = tid; k < BM * CPR; k += 256) {
+        const int ml = k / CPR, c = k - ml * CPR;
+        const long m = m0 + ml;
+        const int n = n0 + c * 8;
+        if (m >= a.M || n >= a.N) continue;
+        *reinterpret_cast<bf16x8*>(a.out + m * a.N + n) = *reinterpret_cast<const bf16x8*>(ot + ml * SP + c * 8);
+    }
+}
+
 // Register staging of one 32-channel chunk of a tile's patch (and of the nine
 // taps of BN output channels' weights).  The per-thread byte offsets of its
 // segments are computed once per tile (and input half) and once per block for
@@ -1830,8 +2029,22 @@ static void launch_gemm_pick(const GemmArgs& a, hipStream_t s, unsigned long lon
 // tuned (accumulating ones would add each candidate's result).
 enum ConvKernel {
     CK_PERS = 0, CK_HALO32, CK_HALO64, CK_GEMM64, CK_GEMM128, CK_SMALLC, CK_FIRST2, CK_GEMM64W, CK_GEMM128W,
-    CK_PERS16, CK_DL64, CK_UPP, CK_COUNT
+    CK_PERS16, CK_DL64, CK_UPP, CK_GPF64, CK_GPF128, CK_COUNT
 };
+
+// The deeper-prefetch implicit GEMM: forward 3 x 3 convolutions writing bf16 (and optionally
+// an FP32 copy), sources of a multiple of 32 channels (so K = 9 C, a multiple of GPF_D
+// chunks), 32-bit byte offsets.
+static bool gemm_pf_ok(const GemmArgs& a) {
+    if (a.gmode != G_CONV || a.epi != E_FWD || !a.out || (a.N & 7) != 0) return false;
+    if (a.c1 <= 0 || (a.c1 & 31) != 0 || (a.c2 & 31) != 0) return false;
+    const int C = a.c1 + a.c2;
+    if (a.K != 9 * C || a.kvalid != a.K || (a.K / KC) % GPF_D != 0) return false;
+    const long s1 = a.abs1 ? (long)a.B * a.abs1 : (long)a.Hi * a.Wi * a.c1;
+    const long s2 = a.abs2 ? (long)a.B * a.abs2 : (long)a.Hi * a.Wi * a.c2;
+    return s1 * 2 < (1L << 31) && s2 * 2 < (1L << 31) && (long)a.N * a.K * 2 < (1L << 31) &&
+           a.M < (1L << 31);
+}
 
 // The persistent up-convolution: K = C_in of 64, 128 or 256, contiguous input, C_out a multiple
 // of 8, 32-bit byte offsets.
@@ -1869,6 +2082,8 @@ static bool ck_applicable(const GemmArgs& a, int ck) {
         case CK_PERS16: return halo && a.N <= 16 && C == HC;   // narrow outputs (the 2-channel head)
         case CK_DL64: return halo && a.N > 32 && a.gmode == G_CONV;   // forward only
         case CK_UPP: return upconv_ok(a);
+        case CK_GPF64: return gemm_pf_ok(a);
+        case CK_GPF128: return gemm_pf_ok(a) && a.N >= 128;
         case CK_SMALLC: return smallc_ok(a);
         case CK_FIRST2: return first2_ok(a);
     }
@@ -1921,6 +2136,15 @@ static int launch_ck(const GemmArgs& a, hipStream_t s, int ck, unsigned long lon
             else
                 launch_halo_ck<0, E_FWD>(a, s, wc, ck);
             break;
+        case CK_GPF64:
+        case CK_GPF128: {
+            const dim3 grid((unsigned)((a.M + 63) / 64), (a.N + (ck == CK_GPF64 ? 63 : 127)) / (ck == CK_GPF64 ? 64 : 128));
+            if (ck == CK_GPF64)
+                TIMED_LAUNCH("k_conv", s, (k_gemm_pf<64, 64, 2, 2>), grid, dim3(256), 0, s, a, wc);
+            else
+                TIMED_LAUNCH("k_conv", s, (k_gemm_pf<64, 128, 2, 2>), grid, dim3(256), 0, s, a, wc);
+            break;
+        }
         case CK_UPP:
             switch (a.c1) {
                 case 64: launch_upconv_k<64>(a, s, wc); break;
