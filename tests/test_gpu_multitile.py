@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 CK_PERS = 0     # the persistent halo kernel's id for helm_conv_force
 CK_DL64 = 10    # the double-buffered direct-load kernel, one 16 x 32 tile per block
+CK_GPF64, CK_GPF128 = 12, 13   # the implicit GEMM with three chunks in flight (64 x 64, 64 x 128 tiles)
 
 
 def bf(x):
@@ -243,3 +244,26 @@ def test_two_stream_preconditioner_matches_one_stream(gpu, precond, use_graph, n
         assert np.all(op.relres(coef, x2[sel], b[sel], med.h, med.h) <= 1e-6)
     with pytest.raises(Exception):
         api.helm_solve(H, bt, tol=1e-6, precond=precond, maxit=5, net=net, streams=3)
+
+
+@pytest.mark.parametrize("ck,H,cin,cout", [(CK_GPF64, 256, 32, 64), (CK_GPF128, 128, 64, 128)])
+def test_prefetch_gemm_stride2_full_size(gpu, ck, H, cin, cout):
+    """The stride-2 layers the autotuner gives to the implicit GEMM with three
+    chunks in flight, at the network's sizes (B = 4: 1024 and 256 tiles of 64
+    output pixels; 9 and 18 chunks of 32 channels), against the oracle."""
+    Bn = 4
+    print("prefetch GEMM stride 2, kernel", ck, "input", H, cin, "->", cout, flush=True)
+    x = rnd((Bn, H, H, cin), 81)
+    Wt = rnd((cout, 3, 3, cin), 82, scale=np.sqrt(2.0 / (9 * cin)))
+    b = rnd((cout,), 83, 0.1)
+    api.helm_conv_force(ck)
+    try:
+        y = api.cnn_layer_forward(0, 2, x, Wt, b, relu=True)
+    finally:
+        api.helm_conv_force(-1)
+    ref = np.maximum(U.conv3x3(x, Wt, b, 2), 0)
+    e = relerr(y, ref)
+    print("rel err", e)
+    assert e <= 1e-5
+    for s in range(Bn):
+        assert relerr(y[s], ref[s]) <= 1e-5
